@@ -1,0 +1,108 @@
+"""The pins are strong enough: plant plausible mistakes in a copy of the
+oracle's C source (a dropped term, a wrong sign, a wrong or transposed index,
+a missing wrap or scale), build each mutant on the CPU, and check that the
+pin checks below reject every one of them while accepting the real oracle."""
+import ctypes
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2004_09883_amd import inputs
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "oracle.c")
+
+MUTANTS = {
+    "dropped_twiddle": ("t[q] = cmul(Y[q * m + k1], tw_at(p, len, q * k1));", "t[q] = Y[q * m + k1];"),
+    "transposed_output": ("X[k1 + m * k2] = acc;", "X[k1 * R + k2] = acc;"),
+    "cmul_sign": ("r.im = a.re * b.im + a.im * b.re;", "r.im = a.re * b.im - a.im * b.re;"),
+    "quadrant_rotation": ("case 1: cr = -s; ci = c;  break;", "case 1: cr = s; ci = c;  break;"),
+    "no_wavenumber_wrap": ("return (2 * i >= n) ? i - n : i;", "return i;"),
+    "evolve_drops_t": ("const double c = four_pi2 * alpha * t;", "const double c = four_pi2 * alpha;"),
+    "checksum_stride": ("const int64_t i = (17 * j) % N;", "const int64_t i = (16 * j) % N;"),
+    "no_inverse_scale": ("data[i] = data[i] / N;", "data[i] = data[i];"),
+    "y_axis_stride": ("if (fft_axis(data, ny, nz, nx * nz, nz, 1, ny * nz, sign))",
+                      "if (fft_axis(data, ny, nz, nx * nz, nz, 1, nx * nz, sign))"),
+    "direct_dft_index": ("acc = cadd(acc, cmul(x[q * s], tw_at(p, len, q * k)));",
+                         "acc = cadd(acc, cmul(x[q], tw_at(p, len, q * k)));"),
+}
+
+
+def _build(tmp_path, name, src_text):
+    d = tmp_path / name
+    d.mkdir()
+    c = d / "oracle.c"
+    c.write_text(src_text)
+    so = d / "lib.so"
+    subprocess.check_call(["gcc", "-O1", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
+                           "-o", str(so), str(c), "-lm"])
+    lib = ctypes.CDLL(str(so))
+    i64, dp, i32 = ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    lib.orc_fft3d.argtypes = [i64, i64, i64, i32, dp]
+    lib.orc_evolve.argtypes = [i64, i64, i64, dp, ctypes.c_double, ctypes.c_double]
+    lib.orc_checksum.argtypes = [i64, i64, i64, dp, dp]
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _dft_matrix(n, sign):
+    r = np.arange(n)
+    return np.exp(sign * 2j * np.pi * (np.outer(r, r) % n) / n)
+
+
+def _dft3d(x, sign):
+    y = np.einsum("kr,abr->abk", _dft_matrix(x.shape[2], sign), x)
+    y = np.einsum("kr,arb->akb", _dft_matrix(x.shape[1], sign), y)
+    y = np.einsum("kr,rab->kab", _dft_matrix(x.shape[0], sign), y)
+    return y / x.size if sign > 0 else y
+
+
+def _pins_pass(lib) -> bool:
+    """Return True iff every pin check accepts this build."""
+    ok = True
+    # 1. transform vs the definition, both directions, non-cubic shape with radix 3
+    x = inputs.uniform_grid((6, 16, 12), 21)
+    for sign in (-1, +1):
+        a = x.copy()
+        lib.orc_fft3d(6, 16, 12, sign, _dp(a))
+        ref = _dft3d(x, sign)
+        ok &= bool(np.linalg.norm(a - ref) / np.linalg.norm(ref) < 1e-14)
+    # 2. evolution of a single mode with wavenumbers above n/2 (closed form)
+    shape, k0, alpha, t = (8, 8, 8), (5, 1, 7), 1e-3, 2.0
+    r = np.indices(shape)
+    x0 = np.exp(2j * np.pi * (sum(r[a] * k0[a] for a in range(3)) % 8) / 8)
+    u = x0.copy()
+    lib.orc_fft3d(8, 8, 8, -1, _dp(u))
+    lib.orc_evolve(8, 8, 8, _dp(u), alpha, t)
+    lib.orc_fft3d(8, 8, 8, +1, _dp(u))
+    ks = [v - 8 if 2 * v >= 8 else v for v in k0]
+    d = np.exp(-4 * np.pi**2 * alpha * t * sum(v * v for v in ks))
+    ok &= bool(np.linalg.norm(u - d * x0) < 1e-13 * np.linalg.norm(x0))
+    # 3. checksum vs a direct loop
+    g = inputs.uniform_grid((32, 32, 32), 3)
+    out = np.zeros(2)
+    lib.orc_checksum(32, 32, 32, _dp(g), _dp(out))
+    flat = g.reshape(-1)
+    want = sum(flat[17 * j] for j in range(1024))
+    ok &= bool(abs(complex(out[0], out[1]) - want) < 1e-12)
+    return ok
+
+
+def test_real_oracle_passes(tmp_path):
+    assert _pins_pass(_build(tmp_path, "orig", open(SRC).read()))
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = open(SRC).read()
+    old, new = MUTANTS[name]
+    assert old in src, f"mutation site for {name} not found"
+    lib = _build(tmp_path, name, src.replace(old, new))
+    assert not _pins_pass(lib)
