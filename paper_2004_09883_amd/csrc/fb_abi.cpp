@@ -1,0 +1,431 @@
+// fb_abi.cpp -- the C ABI of libfb (declared in include/fb.h): argument
+// validation, plans (radix lists, pass geometry, device twiddle tables) and
+// the enqueue order of the passes.
+//
+// The paper's step C-2 (section 3.4) asks that an interface mismatch between
+// the replaced block and the library be surfaced, not papered over: every
+// call validates its arguments on the host before any HIP call and returns a
+// status code with a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "fb.h"
+#include "fb_internal.hpp"
+
+using fb::PassArgs;
+using fb::PassInfo;
+
+namespace {
+
+thread_local int g_code = FB_OK;
+thread_local std::string g_msg;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_code = code;
+    g_msg = buf;
+    return code;
+}
+
+int ok()
+{
+    g_code = FB_OK;
+    g_msg.clear();
+    return FB_OK;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? FB_ERR_OOM : FB_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int esize_of(int dtype) { return dtype == FB_C128 ? 16 : 8; }
+
+// Axis geometry: index 0 = z (contiguous), 1 = y, 2 = x.
+struct AxisPlan {
+    int64_t n;
+    fb::RadixPlan rp;
+    PassInfo pass;
+    size_t tw_off;   // first entry of this axis in the plan's tables
+    int64_t npencils, inner, outer, istep, stride;
+    bool contig;
+};
+
+int check_shape(int64_t nx, int64_t ny, int64_t nz, int dtype)
+{
+    if (dtype != FB_C128 && dtype != FB_C64 && dtype != FB_C64_SPLITBF16)
+        return fail(FB_ERR_DTYPE, "dtype %d is not an fb_dtype value (0, 1 or 2)", dtype);
+    const int64_t d[3] = {nx, ny, nz};
+    const char *nm[3] = {"nx", "ny", "nz"};
+    for (int i = 0; i < 3; i++) {
+        if (d[i] < 1) return fail(FB_ERR_INVALID_ARG, "%s = %lld must be >= 1", nm[i], (long long)d[i]);
+        if (!fb::supported_length(d[i]))
+            return fail(FB_ERR_UNSUPPORTED_SIZE,
+                        "%s = %lld is not supported (axis lengths must be 2^a or 3*2^a, 1..4096)", nm[i],
+                        (long long)d[i]);
+    }
+    return FB_OK;
+}
+
+void build_axes(int64_t nx, int64_t ny, int64_t nz, int esize, AxisPlan ax[3])
+{
+    const int64_t len[3] = {nz, ny, nx};
+    size_t off = 0;
+    for (int a = 0; a < 3; a++) {
+        AxisPlan &A = ax[a];
+        A.n = len[a];
+        A.rp = fb::radix_plan((int)A.n);
+        A.contig = (a == 0);
+        A.pass = A.n > 1 ? fb::find_pass(esize, (int)A.n, A.contig) : PassInfo{nullptr, 0, 0};
+        A.tw_off = off;
+        off += (size_t)A.rp.twlen;
+    }
+    // z: pencils (x, y) back to back
+    ax[0].npencils = nx * ny; ax[0].inner = 1;       ax[0].outer = nz;      ax[0].istep = 0; ax[0].stride = 1;
+    // y: pencils (x, z); base = x ny nz + z
+    ax[1].npencils = nx * nz; ax[1].inner = nz;      ax[1].outer = ny * nz; ax[1].istep = 1; ax[1].stride = nz;
+    // x: pencils (y, z); base = y nz + z
+    ax[2].npencils = ny * nz; ax[2].inner = ny * nz; ax[2].outer = 0;       ax[2].istep = 1; ax[2].stride = ny * nz;
+}
+
+void describe(const AxisPlan ax[3], char *out, size_t cap)
+{
+    std::string s;
+    const char nm[3] = {'z', 'y', 'x'};
+    for (int a = 0; a < 3; a++) {
+        s += nm[a];
+        s += ':';
+        if (ax[a].rp.count == 0) s += '-';
+        for (int i = 0; i < ax[a].rp.count; i++) {
+            if (i) s += ',';
+            s += std::to_string(ax[a].rp.r[i]);
+        }
+        s += ' ';
+    }
+    s += "order:zyx";
+    snprintf(out, cap, "%s", s.c_str());
+}
+
+}  // namespace
+
+struct fb_plan {
+    int64_t nx, ny, nz, N;
+    int dtype, esize;
+    AxisPlan ax[3];
+    double2 *tw64;
+    float2 *tw32;
+    size_t tw_total;
+    int device;
+    char desc[256];
+};
+
+namespace {
+
+int check_plan(const fb_plan *p)
+{
+    if (!p) return fail(FB_ERR_INVALID_ARG, "plan is NULL");
+    return FB_OK;
+}
+
+int check_grid_ptr(const fb_plan *p, const void *ptr, const char *name)
+{
+    if (!ptr) return fail(FB_ERR_INVALID_ARG, "%s is NULL", name);
+    if ((uintptr_t)ptr % (uintptr_t)p->esize)
+        return fail(FB_ERR_INVALID_ARG, "%s is not aligned to the %d-byte element", name, p->esize);
+    return FB_OK;
+}
+
+int check_no_partial_overlap(const fb_plan *p, const void *a, const void *b, bool allow_equal, const char *what)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b, n = (uintptr_t)(p->N * p->esize);
+    if (x == y) return allow_equal ? FB_OK : fail(FB_ERR_INVALID_ARG, "%s: buffers must not alias", what);
+    if (x < y + n && y < x + n) return fail(FB_ERR_INVALID_ARG, "%s: buffers partially overlap", what);
+    return FB_OK;
+}
+
+int check_device(const fb_plan *p)
+{
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != p->device)
+        return fail(FB_ERR_INVALID_ARG, "plan was created on device %d but device %d is current", p->device, cur);
+    return FB_OK;
+}
+
+const void *axis_table(const fb_plan *p, int a)
+{
+    if (p->esize == 16) return p->tw64 + p->ax[a].tw_off;
+    return p->tw32 + p->ax[a].tw_off;
+}
+
+// Largest element index touched by a pass; must stay below N.
+bool pass_in_bounds(const fb_plan *p, const AxisPlan &A)
+{
+    const int64_t np = A.npencils;
+    const int64_t in_max = (np < A.inner ? np : A.inner) - 1;
+    const int64_t max_base = ((np - 1) / A.inner) * A.outer + in_max * A.istep;
+    return max_base + (A.n - 1) * A.stride < p->N && max_base >= 0;
+}
+
+int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, double scale, const PassArgs *ev,
+                hipStream_t st)
+{
+    const AxisPlan &A = p->ax[a];
+    if (!A.pass.launch) return fail(FB_ERR_UNSUPPORTED_SIZE, "no pass for length %lld", (long long)A.n);
+    if (!pass_in_bounds(p, A)) return fail(FB_ERR_INVALID_ARG, "internal: pass geometry out of bounds");
+    PassArgs args{};
+    args.in = in;
+    args.out = out;
+    args.tw = axis_table(p, a);
+    args.npencils = A.npencils;
+    args.inner = A.inner;
+    args.outer = A.outer;
+    args.istep = A.istep;
+    args.stride = A.stride;
+    args.inv = inv;
+    args.scale = scale;
+    if (ev) {
+        args.evolve = 1;
+        args.ev_c = ev->ev_c;
+        args.ev_d = ev->ev_d;
+        args.ev_la = ev->ev_la;
+        args.ev_lb = ev->ev_lb;
+    }
+    hipError_t e = A.pass.launch(args, st);
+    if (e != hipSuccess) return hip_fail(e, "pass launch");
+    return FB_OK;
+}
+
+// Runs the active passes z, y, x.  The first active pass reads `in`; later
+// ones work in place on `out`.  `ev` (optional) fuses the evolution into the
+// first pass, which must then be the contiguous z pass.
+int run_passes(const fb_plan *p, const void *in, void *out, int dir, const PassArgs *ev, hipStream_t st)
+{
+    int last = -1;
+    for (int a = 0; a < 3; a++)
+        if (p->ax[a].n > 1) last = a;
+    if (last < 0) {
+        if (in != out) {
+            hipError_t e = hipMemcpyAsync(out, in, (size_t)p->esize, hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        }
+        return FB_OK;
+    }
+    bool first = true;
+    for (int a = 0; a < 3; a++) {
+        if (p->ax[a].n <= 1) continue;
+        const double scale = (dir > 0 && a == last) ? 1.0 / (double)p->N : 1.0;
+        int rc = launch_axis(p, a, first ? in : out, out, dir > 0, scale, first ? ev : nullptr, st);
+        if (rc) return rc;
+        first = false;
+    }
+    return FB_OK;
+}
+
+int check_alpha_t(double alpha, double t)
+{
+    if (!isfinite(alpha) || alpha < 0) return fail(FB_ERR_INVALID_ARG, "alpha must be finite and >= 0");
+    if (!isfinite(t) || t < 0) return fail(FB_ERR_INVALID_ARG, "t must be finite and >= 0");
+    return FB_OK;
+}
+
+double evolve_c(double alpha, double t)
+{
+    const double four_pi2 = 4.0 * M_PI * M_PI;
+    return four_pi2 * alpha * t;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fb_version(void) { return 100; }
+
+int fb_last_error(const char **msg)
+{
+    if (msg) *msg = g_msg.c_str();
+    return g_code;
+}
+
+int fb_describe_shape(int64_t nx, int64_t ny, int64_t nz, int dtype, char *buf, int cap)
+{
+    if (check_shape(nx, ny, nz, dtype)) return g_code;
+    if (!buf || cap <= 0) return fail(FB_ERR_INVALID_ARG, "buf is NULL or cap <= 0");
+    AxisPlan ax[3];
+    build_axes(nx, ny, nz, esize_of(dtype), ax);
+    char tmp[256];
+    describe(ax, tmp, sizeof tmp);
+    const int len = (int)strlen(tmp);
+    if (len + 1 > cap) return fail(FB_ERR_INVALID_ARG, "buffer too small (%d bytes needed)", len + 1);
+    memcpy(buf, tmp, (size_t)len + 1);
+    ok();
+    return len;
+}
+
+fb_plan *fb_fft3d_plan(int64_t nx, int64_t ny, int64_t nz, int dtype)
+{
+    if (check_shape(nx, ny, nz, dtype)) return nullptr;
+    fb_plan *p = new (std::nothrow) fb_plan();
+    if (!p) {
+        fail(FB_ERR_OOM, "host allocation failed");
+        return nullptr;
+    }
+    p->nx = nx; p->ny = ny; p->nz = nz; p->N = nx * ny * nz;
+    p->dtype = dtype;
+    p->esize = esize_of(dtype);
+    build_axes(nx, ny, nz, p->esize, p->ax);
+    for (int a = 0; a < 3; a++) {
+        if (p->ax[a].n > 1 && !p->ax[a].pass.launch) {
+            fail(FB_ERR_UNSUPPORTED_SIZE, "no pass for length %lld", (long long)p->ax[a].n);
+            delete p;
+            return nullptr;
+        }
+    }
+    describe(p->ax, p->desc, sizeof p->desc);
+    p->tw_total = 0;
+    for (int a = 0; a < 3; a++) p->tw_total += (size_t)p->ax[a].rp.twlen;
+
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        hip_fail(e, "hipGetDevice");
+        delete p;
+        return nullptr;
+    }
+    const size_t nt = p->tw_total > 0 ? p->tw_total : 1;
+    e = hipMalloc((void **)&p->tw64, nt * sizeof(double2));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->tw32, nt * sizeof(float2));
+    if (e != hipSuccess) {
+        hip_fail(e, "hipMalloc (twiddle tables)");
+        fb_fft3d_destroy(p);
+        return nullptr;
+    }
+    for (int a = 0; a < 3 && e == hipSuccess; a++) {
+        const AxisPlan &A = p->ax[a];
+        if (A.rp.twlen == 0) continue;
+        fb::TwDesc d{};
+        d.nst = A.rp.count;
+        for (int s = 0; s < A.rp.count; s++) {
+            d.r[s] = A.rp.r[s];
+            d.ns[s] = A.rp.ns[s];
+            d.off[s] = A.rp.twoff[s];
+        }
+        d.total = A.rp.twlen;
+        e = fb::launch_twiddles(d, p->tw64 + A.tw_off, p->tw32 + A.tw_off, nullptr);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        hip_fail(e, "twiddle generation");
+        fb_fft3d_destroy(p);
+        return nullptr;
+    }
+    ok();
+    return p;
+}
+
+void fb_fft3d_destroy(fb_plan *p)
+{
+    if (!p) return;
+    if (p->tw64) (void)hipFree(p->tw64);
+    if (p->tw32) (void)hipFree(p->tw32);
+    delete p;
+}
+
+size_t fb_plan_device_bytes(const fb_plan *p)
+{
+    if (!p) return 0;
+    const size_t nt = p->tw_total > 0 ? p->tw_total : 1;
+    return nt * (sizeof(double2) + sizeof(float2));
+}
+
+const char *fb_plan_describe(const fb_plan *p)
+{
+    if (!p) {
+        fail(FB_ERR_INVALID_ARG, "plan is NULL");
+        return "";
+    }
+    return p->desc;
+}
+
+fb_status fb_fft3d_exec(const fb_plan *p, const void *in, void *out, int dir, void *hip_stream)
+{
+    if (check_plan(p) || check_grid_ptr(p, in, "in") || check_grid_ptr(p, out, "out")) return (fb_status)g_code;
+    if (dir != FB_FORWARD && dir != FB_INVERSE)
+        return (fb_status)fail(FB_ERR_INVALID_ARG, "dir must be FB_FORWARD (-1) or FB_INVERSE (+1), got %d", dir);
+    if (check_no_partial_overlap(p, in, out, true, "fb_fft3d_exec")) return (fb_status)g_code;
+    if (check_device(p)) return (fb_status)g_code;
+    if (run_passes(p, in, out, dir, nullptr, (hipStream_t)hip_stream)) return (fb_status)g_code;
+    return (fb_status)ok();
+}
+
+fb_status fb_spectral_evolve(const fb_plan *p, void *u, double alpha, double t, void *hip_stream)
+{
+    if (check_plan(p) || check_grid_ptr(p, u, "u") || check_alpha_t(alpha, t)) return (fb_status)g_code;
+    if (check_device(p)) return (fb_status)g_code;
+    hipError_t e = fb::launch_evolve(p->esize, u, u, p->nx, p->ny, p->nz, evolve_c(alpha, t), (hipStream_t)hip_stream);
+    if (e != hipSuccess) return (fb_status)hip_fail(e, "evolve launch");
+    return (fb_status)ok();
+}
+
+fb_status fb_checksum(const fb_plan *p, const void *x, double *out2_dev, void *hip_stream)
+{
+    if (check_plan(p) || check_grid_ptr(p, x, "x")) return (fb_status)g_code;
+    if (!out2_dev || (uintptr_t)out2_dev % 8) return (fb_status)fail(FB_ERR_INVALID_ARG, "out2_dev is NULL or misaligned");
+    if (check_device(p)) return (fb_status)g_code;
+    hipError_t e = fb::launch_checksum(p->esize, x, p->N, out2_dev, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return (fb_status)hip_fail(e, "checksum launch");
+    return (fb_status)ok();
+}
+
+fb_status fb_spectral_step(const fb_plan *p, const void *uhat0, void *x_out, double alpha, double t,
+                           double *out2_dev, void *hip_stream)
+{
+    if (check_plan(p) || check_grid_ptr(p, uhat0, "uhat0") || check_grid_ptr(p, x_out, "x_out") ||
+        check_alpha_t(alpha, t))
+        return (fb_status)g_code;
+    if (out2_dev && (uintptr_t)out2_dev % 8) return (fb_status)fail(FB_ERR_INVALID_ARG, "out2_dev is misaligned");
+    if (check_no_partial_overlap(p, uhat0, x_out, false, "fb_spectral_step")) return (fb_status)g_code;
+    if (check_device(p)) return (fb_status)g_code;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const double c = evolve_c(alpha, t);
+    if (p->nz > 1) {
+        // z pass pencils are (x, y): p = x ny + y
+        PassArgs ev{};
+        ev.ev_c = c;
+        ev.ev_d = p->ny;
+        ev.ev_la = (int)p->nx;
+        ev.ev_lb = (int)p->ny;
+        if (run_passes(p, uhat0, x_out, FB_INVERSE, &ev, st)) return (fb_status)g_code;
+    } else {
+        hipError_t e = fb::launch_evolve(p->esize, uhat0, x_out, p->nx, p->ny, p->nz, c, st);
+        if (e != hipSuccess) return (fb_status)hip_fail(e, "evolve launch");
+        if (run_passes(p, x_out, x_out, FB_INVERSE, nullptr, st)) return (fb_status)g_code;
+    }
+    if (out2_dev) {
+        hipError_t e = fb::launch_checksum(p->esize, x_out, p->N, out2_dev, st);
+        if (e != hipSuccess) return (fb_status)hip_fail(e, "checksum launch");
+    }
+    return (fb_status)ok();
+}
+
+fb_status fb_fill_uniform(const fb_plan *p, void *x, uint64_t seed, void *hip_stream)
+{
+    if (check_plan(p) || check_grid_ptr(p, x, "x")) return (fb_status)g_code;
+    if (check_device(p)) return (fb_status)g_code;
+    hipError_t e = fb::launch_fill_uniform(p->esize, x, p->N, seed, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return (fb_status)hip_fail(e, "fill launch");
+    return (fb_status)ok();
+}
+
+}  // extern "C"

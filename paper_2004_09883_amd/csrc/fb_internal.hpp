@@ -1,0 +1,64 @@
+// fb_internal.hpp -- interface between the C ABI (host) and the kernel
+// translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fb_plan_rules.hpp"
+
+namespace fb {
+
+// Arguments of one pencil pass (see fb_pass.hpp for the geometry).
+struct PassArgs {
+    const void *in;
+    void *out;
+    const void *tw;     // per-stage twiddle table of this axis (same real type as the data)
+    int64_t npencils;
+    int64_t inner, outer, istep, stride;
+    int inv;            // 1: inverse (conjugate on load and on store)
+    double scale;       // applied on store (1/N in the last inverse pass)
+    // fused spectral evolution (contiguous passes only): element i of pencil
+    // p = (pa, pb) with pa = p / ev_d, pb = p % ev_d gets the factor
+    // exp(-ev_c (k(pa; ev_la)^2 + k(pb; ev_lb)^2 + k(i; N)^2))
+    int evolve;
+    double ev_c;
+    int64_t ev_d;
+    int ev_la, ev_lb;
+};
+
+using PassLauncher = hipError_t (*)(const PassArgs &, hipStream_t);
+
+// Geometry of one instantiated pencil pass (for host-side checks).
+struct PassInfo {
+    PassLauncher launch;
+    int pencils_per_wg;
+    int threads;
+};
+
+// esize: 16 (complex128) or 8 (complex64).  Returns launch == nullptr when
+// the length has no instantiated pass.
+PassInfo find_pass(int esize, int n, bool contig);
+
+// Twiddle tables of one axis: for each stage s with ns > 1, entry
+// off[s] + (q-1) ns + k = w_{ns r}^(q k), w_L = exp(-2 pi i / L), in binary64
+// (tw64) and rounded to binary32 (tw32).
+struct TwDesc {
+    int nst;
+    int r[16];
+    int ns[16];
+    int off[16];
+    int total;
+};
+hipError_t launch_twiddles(const TwDesc &d, double2 *tw64, float2 *tw32, hipStream_t st);
+
+// u_out = u_in * exp(-c |k|^2) (u_in may equal u_out).
+hipError_t launch_evolve(int esize, const void *in, void *out, int64_t nx, int64_t ny, int64_t nz,
+                         double c, hipStream_t st);
+
+// out2[0] + i out2[1] = sum_{j<1024} x[(17 j) mod N], fixed-order binary64 tree.
+hipError_t launch_checksum(int esize, const void *x, int64_t N, double *out2, hipStream_t st);
+
+// x[i] = U(seed, 2i) + i U(seed, 2i+1)  (SplitMix64, counter based)
+hipError_t launch_fill_uniform(int esize, void *x, int64_t N, uint64_t seed, hipStream_t st);
+
+}  // namespace fb

@@ -1,0 +1,176 @@
+// fb_misc.hip -- the small kernels around the pencil passes: twiddle-table
+// generation (binary64 on the device), standalone spectral evolution, the
+// strided checksum, and the seeded uniform input generator.
+#include <hip/hip_runtime.h>
+
+#include "fb_device.hpp"
+#include "fb_internal.hpp"
+
+namespace fb {
+
+PassInfo find_pass_c128(int n, bool contig);
+PassInfo find_pass_c64(int n, bool contig);
+
+PassInfo find_pass(int esize, int n, bool contig)
+{
+    if (esize == 16) return find_pass_c128(n, contig);
+    if (esize == 8) return find_pass_c64(n, contig);
+    return {nullptr, 0, 0};
+}
+
+// ---------------------------------------------------------------- twiddles
+
+// exp(-2 pi i m / L) for 0 <= m < L.  The angle is split into whole
+// quadrants and a remainder so that multiples of pi/2 come out exact.
+__device__ double2 root_of_unity(int64_t m, int64_t L)
+{
+    const int64_t m4 = 4 * m;
+    const int64_t quad = m4 / L, rem = m4 - quad * L;   // angle = (pi/2)(quad + rem/L)
+    double s, c;
+    sincospi((double)rem / (2.0 * (double)L), &s, &c);   // sin, cos of (pi/2) rem/L
+    double cr, si;                                        // cos and sin of the full angle
+    switch (quad & 3) {
+    case 0: cr = c;  si = s;  break;
+    case 1: cr = -s; si = c;  break;
+    case 2: cr = -c; si = -s; break;
+    default: cr = s; si = -c; break;
+    }
+    return make_double2(cr, -si);
+}
+
+__global__ void twiddle_kernel(TwDesc d, double2 *tw64, float2 *tw32)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= d.total) return;
+    int s = -1;   // the stage owning entry e (stages with ns == 1 own none)
+    for (int i = 0; i < d.nst; i++)
+        if (d.ns[i] > 1 && e >= d.off[i] && e < d.off[i] + (d.r[i] - 1) * d.ns[i]) s = i;
+    if (s < 0) return;
+    const int local = e - d.off[s];
+    const int q = 1 + local / d.ns[s];
+    const int k = local % d.ns[s];
+    const int64_t L = (int64_t)d.ns[s] * d.r[s];
+    const double2 w = root_of_unity(((int64_t)q * k) % L, L);
+    tw64[e] = w;
+    tw32[e] = make_float2((float)w.x, (float)w.y);
+}
+
+hipError_t launch_twiddles(const TwDesc &d, double2 *tw64, float2 *tw32, hipStream_t st)
+{
+    if (d.total <= 0) return hipSuccess;
+    const int threads = 256;
+    const int blocks = (d.total + threads - 1) / threads;
+    hipLaunchKernelGGL(twiddle_kernel, dim3(blocks), dim3(threads), 0, st, d, tw64, tw32);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- evolution
+
+__device__ __forceinline__ int64_t wrapped(int64_t i, int64_t n) { return (2 * i >= n) ? i - n : i; }
+
+// One thread per element of a z row; block (bx, iy, ix).
+template <typename V, typename R>
+__global__ void evolve_kernel(const V *in, V *out, int64_t nx, int64_t ny, int64_t nz, double c)
+{
+    const int64_t iz = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t iy = blockIdx.y, ix = blockIdx.z;
+    if (iz >= nz) return;
+    const int64_t kx = wrapped(ix, nx), ky = wrapped(iy, ny), kz = wrapped(iz, nz);
+    const double k2 = (double)(kx * kx + ky * ky + kz * kz);
+    const R f = evol_factor<R>(c, k2);
+    const int64_t i = (ix * ny + iy) * nz + iz;
+    V v = in[i];
+    v.x *= f;
+    v.y *= f;
+    out[i] = v;
+}
+
+hipError_t launch_evolve(int esize, const void *in, void *out, int64_t nx, int64_t ny, int64_t nz,
+                         double c, hipStream_t st)
+{
+    const int threads = nz >= 256 ? 256 : (int)((nz + 63) / 64) * 64;
+    const dim3 grid((unsigned)((nz + threads - 1) / threads), (unsigned)ny, (unsigned)nx);
+    if (esize == 16)
+        hipLaunchKernelGGL((evolve_kernel<double2, double>), grid, dim3(threads), 0, st,
+                           (const double2 *)in, (double2 *)out, nx, ny, nz, c);
+    else
+        hipLaunchKernelGGL((evolve_kernel<float2, float>), grid, dim3(threads), 0, st,
+                           (const float2 *)in, (float2 *)out, nx, ny, nz, c);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- checksum
+
+// 1024 threads; thread j loads x[(17 j) mod N]; pairwise tree in binary64.
+template <typename V>
+__global__ void __launch_bounds__(1024) checksum_kernel(const V *x, int64_t N, double *out2)
+{
+    __shared__ double sr[1024], si[1024];
+    const int j = threadIdx.x;
+    const V v = x[(17 * (int64_t)j) % N];
+    sr[j] = (double)v.x;
+    si[j] = (double)v.y;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if (j < h) {
+            sr[j] += sr[j + h];
+            si[j] += si[j + h];
+        }
+        __syncthreads();
+    }
+    if (j == 0) {
+        out2[0] = sr[0];
+        out2[1] = si[0];
+    }
+}
+
+hipError_t launch_checksum(int esize, const void *x, int64_t N, double *out2, hipStream_t st)
+{
+    if (esize == 16)
+        hipLaunchKernelGGL((checksum_kernel<double2>), dim3(1), dim3(1024), 0, st, (const double2 *)x, N, out2);
+    else
+        hipLaunchKernelGGL((checksum_kernel<float2>), dim3(1), dim3(1024), 0, st, (const float2 *)x, N, out2);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- inputs
+
+// SplitMix64 (Steele, Lea, Flood 2014) at counter c of stream `seed`:
+// the (c+1)-th output of the sequential generator started at state `seed`.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c)
+{
+    uint64_t z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double u_pm1(uint64_t h) { return (double)(h >> 11) * 0x1.0p-52 - 1.0; }
+
+template <typename V, typename R>
+__global__ void fill_uniform_kernel(V *x, int64_t N, uint64_t seed)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        V v;
+        v.x = (R)u_pm1(splitmix64_at(seed, 2 * (uint64_t)i));
+        v.y = (R)u_pm1(splitmix64_at(seed, 2 * (uint64_t)i + 1));
+        x[i] = v;
+    }
+}
+
+hipError_t launch_fill_uniform(int esize, void *x, int64_t N, uint64_t seed, hipStream_t st)
+{
+    const int threads = 256;
+    int64_t blocks = (N + threads - 1) / threads;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    if (esize == 16)
+        hipLaunchKernelGGL((fill_uniform_kernel<double2, double>), dim3((unsigned)blocks), dim3(threads), 0, st,
+                           (double2 *)x, N, seed);
+    else
+        hipLaunchKernelGGL((fill_uniform_kernel<float2, float>), dim3((unsigned)blocks), dim3(threads), 0, st,
+                           (float2 *)x, N, seed);
+    return hipGetLastError();
+}
+
+}  // namespace fb

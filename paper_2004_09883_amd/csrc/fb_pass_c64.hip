@@ -1,0 +1,6 @@
+// Pencil passes for complex64 grids (binary32 arithmetic).
+#include "fb_pass_inst.hpp"
+
+namespace fb {
+PassInfo find_pass_c64(int n, bool contig) { return find_pass_t<float2>(n, contig); }
+}  // namespace fb

@@ -1,0 +1,39 @@
+// fb_pass_inst.hpp -- instantiates the pencil passes of one element type for
+// every supported axis length (2^a and 3*2^a up to 4096) and builds the
+// length -> launcher table.
+#pragma once
+#include "fb_internal.hpp"
+#include "fb_pass.hpp"
+
+namespace fb {
+
+template <typename V, int N, bool CONTIG> hipError_t launch_pass(const PassArgs &a, hipStream_t st)
+{
+    using Cfg = PassCfg<V, N, CONTIG>;
+    const int64_t blocks = (a.npencils + Cfg::P - 1) / Cfg::P;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((fft_pass<V, N, CONTIG>), dim3((unsigned)blocks), dim3(Cfg::THREADS), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename V, int N> PassInfo pass_info(bool contig)
+{
+    if (contig) return {&launch_pass<V, N, true>, PassCfg<V, N, true>::P, PassCfg<V, N, true>::THREADS};
+    return {&launch_pass<V, N, false>, PassCfg<V, N, false>::P, PassCfg<V, N, false>::THREADS};
+}
+
+#define FB_FOR_EACH_LENGTH(X) \
+    X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) \
+    X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096)
+
+template <typename V> PassInfo find_pass_t(int n, bool contig)
+{
+    switch (n) {
+#define FB_CASE(L) case L: return pass_info<V, L>(contig);
+        FB_FOR_EACH_LENGTH(FB_CASE)
+#undef FB_CASE
+    default: return {nullptr, 0, 0};
+    }
+}
+
+}  // namespace fb

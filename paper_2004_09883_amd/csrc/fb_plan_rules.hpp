@@ -1,0 +1,93 @@
+// fb_plan_rules.hpp -- compile-time and host-side rules of the plan: the radix
+// list of an axis length and the launch geometry of a pencil pass.
+//
+// Radix list of n = 2^a 3^b, in the order the stages are applied to the data:
+// b threes, then floor(a/4) sixteens, then 2^(a mod 4) when a mod 4 > 0
+// (e.g. 512 -> 16,16,2; 768 -> 3,16,16; 64 -> 16,4).  The library supports
+// b <= 1 (n = 2^a or 3*2^a) and n <= 4096 on a 3D axis.
+#pragma once
+#include <stdint.h>
+
+namespace fb {
+
+struct RadixPlan {
+    int count;
+    int r[16];
+    int ns[16];     // product of the radices before stage s
+    int twoff[16];  // offset of stage s in the per-axis twiddle table
+    int twlen;      // total twiddle entries
+};
+
+constexpr RadixPlan radix_plan(int n)
+{
+    RadixPlan p{};
+    p.count = 0;
+    int a = 0, b = 0, m = n;
+    while (m > 1 && m % 3 == 0) { m /= 3; b++; }
+    while (m > 1 && m % 2 == 0) { m /= 2; a++; }
+    if (m != 1 || n < 1) { p.count = -1; return p; }
+    for (int i = 0; i < b; i++) p.r[p.count++] = 3;
+    for (int i = 0; i < a / 4; i++) p.r[p.count++] = 16;
+    if (a % 4) p.r[p.count++] = 1 << (a % 4);
+    int ns = 1, off = 0;
+    for (int s = 0; s < p.count; s++) {
+        p.ns[s] = ns;
+        p.twoff[s] = off;
+        if (ns > 1) off += (p.r[s] - 1) * ns;  // entries w_{ns r}^(q k), 1<=q<r, k<ns
+        ns *= p.r[s];
+    }
+    p.twlen = off;
+    return p;
+}
+
+// True when n is an axis length the 3D passes support.
+constexpr bool supported_length(int64_t n)
+{
+    if (n < 1 || n > 4096) return false;
+    int64_t m = n;
+    if (m % 3 == 0) m /= 3;
+    while (m % 2 == 0) m /= 2;
+    return m == 1;
+}
+
+// Threads that cooperate on one pencil: each holds about 16 elements.
+constexpr int threads_per_pencil(int n) { return (n % 16 == 0) ? n / 16 : 1; }
+
+// Largest number of elements one thread holds over all stages.
+constexpr int regs_per_thread(int n)
+{
+    RadixPlan p = radix_plan(n);
+    int T = threads_per_pencil(n), M = 0;
+    for (int s = 0; s < p.count; s++) {
+        int nbf = n / p.r[s];
+        int u = (nbf + T - 1) / T;
+        if (u * p.r[s] > M) M = u * p.r[s];
+    }
+    return M;
+}
+
+// LDS row of one pencil: one pad element every 16 (breaks the stride-R
+// pattern of the first exchange) and an odd total (consecutive pencils land
+// on different banks).
+constexpr int lds_pencil_stride(int n)
+{
+    int s = n + n / 16;
+    return (s % 2 == 0) ? s + 1 : s;
+}
+
+constexpr int lds_budget_bytes(bool contig) { return contig ? 40 * 1024 : 72 * 1024; }
+
+// Pencils per workgroup.  Contiguous passes aim for 256 threads; strided
+// passes aim for 16 (c128) / 32 (c64) adjacent pencils so that every row
+// access is a 256-byte segment.  Both are capped by 1024 threads and by the
+// LDS budget.
+constexpr int pencils_per_wg(int n, bool contig, int esize)
+{
+    const int T = threads_per_pencil(n);
+    int P = contig ? (256 / T > 0 ? 256 / T : 1) : (esize == 16 ? 16 : 32);
+    if (!contig && T == 1) P = 64;
+    while (P > 1 && (P * T > 1024 || P * lds_pencil_stride(n) * esize > lds_budget_bytes(contig))) P /= 2;
+    return P;
+}
+
+}  // namespace fb

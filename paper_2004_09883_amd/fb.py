@@ -1,0 +1,204 @@
+"""Python binding of libfb (ctypes; argument marshalling only).
+
+Each function carries the name of the C entry point it calls (include/fb.h).
+Grid arguments are torch tensors on the plan's device (complex128 for
+FB_C128, complex64 otherwise, C-contiguous, shape (nx, ny, nz)) or raw
+device addresses (int).  Work is enqueued on ``stream`` (a torch.cuda.Stream,
+a raw hipStream_t int, or None for torch's current stream).  Every step of
+the computation runs in libfb's HIP kernels; if the library is not built the
+binding raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfb.so")
+
+FB_C128, FB_C64, FB_C64_SPLITBF16 = 0, 1, 2
+FB_FORWARD, FB_INVERSE = -1, +1
+FB_OK = 0
+FB_ERR_INVALID_ARG = -1
+FB_ERR_UNSUPPORTED_SIZE = -2
+FB_ERR_DTYPE = -3
+FB_ERR_OOM = -4
+FB_ERR_DEVICE = -5
+FB_ERR_BUDGET = -6
+
+DTYPE_NAMES = {FB_C128: "c128", FB_C64: "c64", FB_C64_SPLITBF16: "c64_splitbf16"}
+
+# every entry point declared in include/fb.h
+EXPORTS = ("fb_version", "fb_last_error", "fb_describe_shape", "fb_fft3d_plan", "fb_fft3d_destroy",
+           "fb_plan_device_bytes", "fb_plan_describe", "fb_fft3d_exec", "fb_spectral_evolve",
+           "fb_checksum", "fb_spectral_step", "fb_fill_uniform")
+
+
+class FbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fb error {code}: {msg}")
+        self.code = code
+        self.msg = msg
+
+
+_lib = None
+
+
+def load():
+    """Load libfb.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FbError(FB_ERR_DEVICE, f"{LIB_PATH} is not built (run __graft_entry__.build() or "
+                                     "python -m paper_2004_09883_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64, vp, i32, dbl = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "fb_version": (i32, []),
+        "fb_last_error": (i32, [ctypes.POINTER(ctypes.c_char_p)]),
+        "fb_describe_shape": (i32, [i64, i64, i64, i32, ctypes.c_char_p, i32]),
+        "fb_fft3d_plan": (vp, [i64, i64, i64, i32]),
+        "fb_fft3d_destroy": (None, [vp]),
+        "fb_plan_device_bytes": (ctypes.c_size_t, [vp]),
+        "fb_plan_describe": (ctypes.c_char_p, [vp]),
+        "fb_fft3d_exec": (i32, [vp, vp, vp, i32, vp]),
+        "fb_spectral_evolve": (i32, [vp, vp, dbl, dbl, vp]),
+        "fb_checksum": (i32, [vp, vp, vp, vp]),
+        "fb_spectral_step": (i32, [vp, vp, vp, dbl, dbl, vp, vp]),
+        "fb_fill_uniform": (i32, [vp, vp, ctypes.c_uint64, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def fb_last_error():
+    msg = ctypes.c_char_p()
+    code = load().fb_last_error(ctypes.byref(msg))
+    return code, (msg.value or b"").decode()
+
+
+def _check(rc: int):
+    if rc < 0:
+        code, msg = fb_last_error()
+        raise FbError(rc, msg)
+    return rc
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def fb_version() -> int:
+    return load().fb_version()
+
+
+def fb_describe_shape(nx: int, ny: int, nz: int, dtype: int = FB_C128) -> str:
+    buf = ctypes.create_string_buffer(256)
+    _check(load().fb_describe_shape(nx, ny, nz, dtype, buf, 256))
+    return buf.value.decode()
+
+
+class Plan:
+    """Owns an fb_plan*; destroyed with the object or by close()."""
+
+    def __init__(self, nx: int, ny: int, nz: int, dtype: int = FB_C128):
+        self._lib = load()
+        h = self._lib.fb_fft3d_plan(nx, ny, nz, dtype)
+        if not h:
+            code, msg = fb_last_error()
+            raise FbError(code, msg)
+        self.handle = h
+        self.shape = (nx, ny, nz)
+        self.dtype = dtype
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.fb_fft3d_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.complex128 if self.dtype == FB_C128 else torch.complex64
+
+    def check_tensor(self, x, name="x"):
+        """Shape/dtype/contiguity check of a torch tensor argument."""
+        if isinstance(x, int):
+            return
+        if tuple(x.shape) != self.shape:
+            raise FbError(FB_ERR_INVALID_ARG, f"{name} has shape {tuple(x.shape)}, plan is {self.shape}")
+        if x.dtype != self.torch_dtype:
+            raise FbError(FB_ERR_DTYPE, f"{name} is {x.dtype}, plan needs {self.torch_dtype}")
+        if not x.is_contiguous():
+            raise FbError(FB_ERR_INVALID_ARG, f"{name} must be C-contiguous")
+        if not x.is_cuda:
+            raise FbError(FB_ERR_INVALID_ARG, f"{name} must be a device tensor")
+
+
+def fb_fft3d_plan(nx: int, ny: int, nz: int, dtype: int = FB_C128) -> Plan:
+    return Plan(nx, ny, nz, dtype)
+
+
+def fb_fft3d_destroy(plan: Plan):
+    plan.close()
+
+
+def fb_plan_device_bytes(plan: Plan) -> int:
+    return int(load().fb_plan_device_bytes(plan.handle))
+
+
+def fb_plan_describe(plan: Plan) -> str:
+    return load().fb_plan_describe(plan.handle).decode()
+
+
+def fb_fft3d_exec(plan: Plan, x_in, x_out, direction: int = FB_FORWARD, stream=None):
+    plan.check_tensor(x_in, "in")
+    plan.check_tensor(x_out, "out")
+    _check(load().fb_fft3d_exec(plan.handle, _ptr(x_in), _ptr(x_out), direction, _stream(stream)))
+
+
+def fb_spectral_evolve(plan: Plan, u, alpha: float, t: float, stream=None):
+    plan.check_tensor(u, "u")
+    _check(load().fb_spectral_evolve(plan.handle, _ptr(u), float(alpha), float(t), _stream(stream)))
+
+
+def fb_checksum(plan: Plan, x, out2, stream=None):
+    """out2: a float64 device tensor with at least 2 elements (or an address)."""
+    plan.check_tensor(x, "x")
+    _check(load().fb_checksum(plan.handle, _ptr(x), _ptr(out2), _stream(stream)))
+
+
+def fb_spectral_step(plan: Plan, uhat0, x_out, alpha: float, t: float, out2=None, stream=None):
+    plan.check_tensor(uhat0, "uhat0")
+    plan.check_tensor(x_out, "x_out")
+    _check(load().fb_spectral_step(plan.handle, _ptr(uhat0), _ptr(x_out), float(alpha), float(t),
+                                   _ptr(out2), _stream(stream)))
+
+
+def fb_fill_uniform(plan: Plan, x, seed: int, stream=None):
+    plan.check_tensor(x, "x")
+    _check(load().fb_fill_uniform(plan.handle, _ptr(x), int(seed) & 0xFFFFFFFFFFFFFFFF, _stream(stream)))

@@ -1,0 +1,87 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+entry point the header declares, describes plans exactly as the oracle's
+radix rule does, and rejects invalid arguments before touching the device
+(the paper's step C-2, section 3.4: a mismatched interface is reported, not
+coerced)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_2004_09883_amd import fb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "fb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fb_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fb.load()
+    names = header_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(fb.EXPORTS) == names
+
+
+def test_version():
+    assert fb.fb_version() >= 100
+
+
+SHAPES = [(512, 256, 256), (256, 256, 128), (64, 64, 64), (32, 32, 32), (128, 256, 512), (1, 512, 512),
+          (1, 1, 1), (3, 6, 12), (4096, 2, 1), (768, 96, 24), (1, 3072, 48), (2, 1, 1536)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_describe_matches_oracle(shape):
+    for dt in (fb.FB_C128, fb.FB_C64, fb.FB_C64_SPLITBF16):
+        assert fb.fb_describe_shape(*shape, dt) == oracle.describe(*shape)
+
+
+@pytest.mark.parametrize("shape,code", [((0, 4, 4), fb.FB_ERR_INVALID_ARG), ((4, -1, 4), fb.FB_ERR_INVALID_ARG),
+                                        ((5, 4, 4), fb.FB_ERR_UNSUPPORTED_SIZE),
+                                        ((4, 4, 8192), fb.FB_ERR_UNSUPPORTED_SIZE),
+                                        ((4, 9, 4), fb.FB_ERR_UNSUPPORTED_SIZE),
+                                        ((4, 4, 6144), fb.FB_ERR_UNSUPPORTED_SIZE)])
+def test_describe_rejects_shapes(shape, code):
+    with pytest.raises(fb.FbError) as e:
+        fb.fb_describe_shape(*shape)
+    assert e.value.code == code
+    assert fb.fb_last_error()[0] == code
+
+
+def test_describe_rejects_dtype():
+    with pytest.raises(fb.FbError) as e:
+        fb.fb_describe_shape(8, 8, 8, 7)
+    assert e.value.code == fb.FB_ERR_DTYPE
+    assert "dtype" in e.value.msg
+
+
+def test_plan_rejects_before_device():
+    lib = fb.load()
+    assert not lib.fb_fft3d_plan(6, 5, 4, 0)
+    assert fb.fb_last_error()[0] == fb.FB_ERR_UNSUPPORTED_SIZE
+    assert not lib.fb_fft3d_plan(8, 8, 8, 3)
+    assert fb.fb_last_error()[0] == fb.FB_ERR_DTYPE
+
+
+def test_null_plan_calls_are_rejected():
+    lib = fb.load()
+    assert lib.fb_fft3d_exec(None, 16, 16, -1, None) == fb.FB_ERR_INVALID_ARG
+    assert lib.fb_spectral_evolve(None, 16, 1e-6, 1.0, None) == fb.FB_ERR_INVALID_ARG
+    assert lib.fb_checksum(None, 16, 16, None) == fb.FB_ERR_INVALID_ARG
+    assert lib.fb_spectral_step(None, 16, 4096, 1e-6, 1.0, None, None) == fb.FB_ERR_INVALID_ARG
+    assert lib.fb_fill_uniform(None, 16, 1, None) == fb.FB_ERR_INVALID_ARG
+    assert lib.fb_plan_device_bytes(None) == 0
+    lib.fb_fft3d_destroy(None)   # NULL-safe
+
+
+def test_last_error_clears_on_success():
+    fb.fb_describe_shape(8, 8, 8)
+    assert fb.fb_last_error() == (0, "")

@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs.
+
+Bars (relative L2 over the whole grid, per step): complex128 path <= 1e-12,
+complex64 path <= 1e-5; checksums are compared with the error normalised by
+sum_j |x_ref[17 j]|.  The oracle follows the Fourier-transform block of the
+paper (section 5.1(a)) re-created as the 3D spectral block.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_09883_amd import fb, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = {fb.FB_C128: 1e-12, fb.FB_C64: 1e-5}
+LENGTHS = [2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096]
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(x, dtype):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    t = t.to(torch.complex128 if dtype == fb.FB_C128 else torch.complex64)
+    return t.cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def as_seen(x, dtype):
+    """The values the device holds for a host grid (c64 rounds each part)."""
+    return x if dtype == fb.FB_C128 else inputs.round_c64(x).astype(np.complex128)
+
+
+def checksum_err(got, ref_grid):
+    flat = ref_grid.reshape(-1)
+    idx = (17 * np.arange(1024)) % flat.size
+    return abs(got - oracle.checksum(ref_grid)) / np.sum(np.abs(flat[idx]))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "these tests need a GPU"
+    fb.load()
+    print("device:", torch.cuda.get_device_name(0), flush=True)
+
+
+def run_fft(shape, dtype, seed=1, direction=fb.FB_FORWARD, inplace=False):
+    x = inputs.uniform_grid(shape, seed)
+    xs = as_seen(x, dtype)
+    plan = fb.Plan(*shape, dtype)
+    xin = dev(x, dtype)
+    out = xin if inplace else torch.empty_like(xin)
+    fb.fb_fft3d_exec(plan, xin, out, direction)
+    got = host(out)
+    ref = oracle.fft3d(xs, direction)
+    return got, ref
+
+
+# ---------------------------------------------------------------- one axis at a time
+
+@pytest.mark.parametrize("dtype", [fb.FB_C128, fb.FB_C64])
+@pytest.mark.parametrize("n", LENGTHS)
+@pytest.mark.parametrize("axis", ["z", "y", "x"])
+def test_single_axis_pass(axis, n, dtype):
+    shape = {"z": (1, 3, n), "y": (2, n, 6), "x": (n, 3, 4)}[axis]
+    print(f"axis={axis} n={n} dtype={dtype} shape={shape}", flush=True)
+    for direction in (fb.FB_FORWARD, fb.FB_INVERSE):
+        got, ref = run_fft(shape, dtype, seed=n, direction=direction)
+        assert rel_l2(got, ref) < TOL[dtype], (axis, n, direction)
+
+
+# ---------------------------------------------------------------- whole 3D transforms
+
+SHAPES_3D = [(64, 64, 64), (32, 48, 96), (12, 96, 24), (3, 6, 12), (1, 1, 1), (1, 1, 4096), (4096, 1, 2),
+             (2, 4096, 1), (128, 256, 512), (256, 256, 128)]
+
+
+@pytest.mark.parametrize("dtype", [fb.FB_C128, fb.FB_C64])
+@pytest.mark.parametrize("shape", SHAPES_3D)
+def test_fft3d(shape, dtype):
+    print(f"fft3d shape={shape} dtype={dtype}", flush=True)
+    for direction in (fb.FB_FORWARD, fb.FB_INVERSE):
+        got, ref = run_fft(shape, dtype, seed=7, direction=direction)
+        assert rel_l2(got, ref) < TOL[dtype], direction
+
+
+@pytest.mark.parametrize("dtype", [fb.FB_C128, fb.FB_C64])
+def test_fft3d_in_place_equals_out_of_place(dtype):
+    shape = (32, 64, 48)
+    a, ref = run_fft(shape, dtype, seed=3)
+    b, _ = run_fft(shape, dtype, seed=3, inplace=True)
+    assert np.array_equal(a, b)
+    assert rel_l2(a, ref) < TOL[dtype]
+
+
+def test_round_trip_c128():
+    shape = (64, 32, 96)
+    x = inputs.uniform_grid(shape, 5)
+    plan = fb.Plan(*shape, fb.FB_C128)
+    t = dev(x, fb.FB_C128)
+    fb.fb_fft3d_exec(plan, t, t, fb.FB_FORWARD)
+    fb.fb_fft3d_exec(plan, t, t, fb.FB_INVERSE)
+    assert rel_l2(host(t), x) < 1e-14
+
+
+def test_fft3d_config3_full_size_c128():
+    """512 x 256 x 256 complex128, Gaussian input: the shape and launch
+    configuration the benchmark times."""
+    shape = (512, 256, 256)
+    x = inputs.gaussian_grid(shape, 2)
+    plan = fb.Plan(*shape, fb.FB_C128)
+    t = dev(x, fb.FB_C128)
+    out = torch.empty_like(t)
+    fb.fb_fft3d_exec(plan, t, out, fb.FB_FORWARD)
+    got = host(out)
+    del out, t
+    ref = oracle.fft3d(x, -1)
+    assert rel_l2(got, ref) < 1e-12
+
+
+# ---------------------------------------------------------------- evolve / checksum / inputs
+
+@pytest.mark.parametrize("dtype", [fb.FB_C128, fb.FB_C64])
+def test_evolve_standalone(dtype):
+    shape = (16, 24, 32)
+    u = inputs.uniform_grid(shape, 9)
+    plan = fb.Plan(*shape, dtype)
+    t = dev(u, dtype)
+    fb.fb_spectral_evolve(plan, t, 1e-3, 2.5)
+    ref = oracle.evolve(as_seen(u, dtype), 1e-3, 2.5)
+    assert rel_l2(host(t), ref) < (1e-15 if dtype == fb.FB_C128 else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", [fb.FB_C128, fb.FB_C64])
+@pytest.mark.parametrize("shape", [(32, 32, 32), (4, 4, 4), (512, 256, 256)])
+def test_checksum(shape, dtype):
+    x = inputs.uniform_grid(shape, 4)
+    plan = fb.Plan(*shape, dtype)
+    t = dev(x, dtype)
+    out2 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    fb.fb_checksum(plan, t, out2)
+    got = complex(*out2.cpu().numpy())
+    assert checksum_err(got, as_seen(x, dtype)) < 1e-15
+
+
+@pytest.mark.parametrize("dtype", [fb.FB_C128, fb.FB_C64])
+def test_fill_uniform_bitwise(dtype):
+    shape = (8, 12, 48)
+    plan = fb.Plan(*shape, dtype)
+    t = torch.empty(shape, dtype=plan.torch_dtype, device="cuda")
+    fb.fb_fill_uniform(plan, t, 12345)
+    want = inputs.uniform_grid(shape, 12345)
+    if dtype == fb.FB_C64:
+        want = inputs.round_c64(want)
+    assert np.array_equal(t.cpu().numpy(), want)
+
+
+# ---------------------------------------------------------------- the spectral block
+
+def spectral_block_gpu(x0, dtype, alpha, steps, fused=True):
+    shape = x0.shape
+    plan = fb.Plan(*shape, dtype)
+    u0 = dev(x0, dtype)
+    fb.fb_fft3d_exec(plan, u0, u0, fb.FB_FORWARD)
+    xt = torch.empty_like(u0)
+    sums = torch.zeros((steps, 2), dtype=torch.float64, device="cuda")
+    grids = []
+    for t in range(1, steps + 1):
+        if fused:
+            fb.fb_spectral_step(plan, u0, xt, alpha, t, sums[t - 1])
+        else:
+            xt.copy_(u0)
+            fb.fb_spectral_evolve(plan, xt, alpha, t)
+            fb.fb_fft3d_exec(plan, xt, xt, fb.FB_INVERSE)
+            fb.fb_checksum(plan, xt, sums[t - 1])
+        grids.append(host(xt))
+    s = sums.cpu().numpy()
+    return s[:, 0] + 1j * s[:, 1], grids
+
+
+def check_block(shape, dtype, seed, alpha, steps, fused=True, gaussian=False):
+    x0 = inputs.gaussian_grid(shape, seed) if gaussian else inputs.uniform_grid(shape, seed)
+    sums, grids = spectral_block_gpu(x0, dtype, alpha, steps, fused)
+    X0 = oracle.fft3d(as_seen(x0, dtype), -1)
+    worst = 0.0
+    for t in range(1, steps + 1):
+        ref = oracle.fft3d(oracle.evolve(X0, alpha, t), +1)
+        e = rel_l2(grids[t - 1], ref)
+        worst = max(worst, e)
+        assert e < TOL[dtype], (t, e)
+        assert checksum_err(sums[t - 1], ref) < TOL[dtype], t
+    print(f"block shape={shape} dtype={dtype} worst rel L2 {worst:.3e}")
+
+
+def test_block_64cube_c128_fused():
+    check_block((64, 64, 64), fb.FB_C128, seed=1, alpha=1e-6, steps=6)
+
+
+def test_block_64cube_c128_unfused():
+    check_block((64, 64, 64), fb.FB_C128, seed=1, alpha=1e-6, steps=6, fused=False)
+
+
+def test_block_strong_decay_and_nz1_fallback():
+    check_block((32, 64, 1), fb.FB_C128, seed=8, alpha=1e-3, steps=3)
+    check_block((24, 12, 48), fb.FB_C128, seed=8, alpha=1e-3, steps=3)
+
+
+def test_block_c64():
+    check_block((64, 64, 64), fb.FB_C64, seed=1, alpha=1e-6, steps=6)
+    check_block((128, 64, 96), fb.FB_C64, seed=2, alpha=1e-6, steps=3, gaussian=True)
+
+
+def test_block_256x256x128_c128_20_steps():
+    """The 256 x 256 x 128 complex128 workload with 20 steps, alpha = 1e-6."""
+    check_block((256, 256, 128), fb.FB_C128, seed=1, alpha=1e-6, steps=20)
+
+
+def test_plan_describe_matches_oracle_on_device():
+    plan = fb.Plan(256, 256, 128, fb.FB_C128)
+    assert fb.fb_plan_describe(plan) == oracle.describe(256, 256, 128)
+    assert fb.fb_plan_device_bytes(plan) > 0
+
+
+def test_wrong_device_tensor_shape_rejected():
+    plan = fb.Plan(8, 8, 8, fb.FB_C128)
+    t = torch.zeros((8, 8, 4), dtype=torch.complex128, device="cuda")
+    with pytest.raises(fb.FbError):
+        fb.fb_fft3d_exec(plan, t, t)
+
+
+def test_partial_overlap_rejected():
+    plan = fb.Plan(8, 8, 8, fb.FB_C128)
+    buf = torch.zeros(1024, dtype=torch.complex128, device="cuda")
+    lib = fb.load()
+    rc = lib.fb_fft3d_exec(plan.handle, buf.data_ptr(), buf.data_ptr() + 16 * 100, -1, None)
+    assert rc == fb.FB_ERR_INVALID_ARG
+    rc = lib.fb_fft3d_exec(plan.handle, buf.data_ptr() + 8, buf.data_ptr(), -1, None)
+    assert rc == fb.FB_ERR_INVALID_ARG   # misaligned
