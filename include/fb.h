@@ -102,6 +102,13 @@ const char *fb_plan_describe(const fb_plan *p);
  * partially overlapping buffers are rejected.  Needs no workspace. */
 fb_status fb_fft3d_exec(const fb_plan *p, const void *in, void *out, int dir, void *hip_stream);
 
+/* The same transform restricted to some axes: bit 0 of `axes` selects z,
+ * bit 1 y, bit 2 x (axes = 7 is fb_fft3d_exec).  The inverse divides by the
+ * product of the selected lengths.  With no axis of length > 1 selected the
+ * call copies in to out.  Same buffer rules as fb_fft3d_exec. */
+fb_status fb_fft3d_exec_axes(const fb_plan *p, const void *in, void *out, int dir, int axes,
+                             void *hip_stream);
+
 /* Spectral evolution in place: u[k] *= exp(-(4 pi^2 alpha t) |k|^2), with
  * the signed wavenumber k = i - n [2i >= n] on each axis (heat-equation decay
  * of each Fourier mode on the unit periodic cube).  alpha >= 0, t >= 0,
@@ -126,6 +133,19 @@ fb_status fb_spectral_step(const fb_plan *p, const void *uhat0, void *x_out, dou
  * with h the SplitMix64 output at counter c of stream s (complex64 grids get
  * the binary64 values rounded to nearest). */
 fb_status fb_fill_uniform(const fb_plan *p, void *x, uint64_t seed, void *hip_stream);
+
+/* Per-launch timing of the library's kernels, for benchmarks.  While
+ * enabled, every kernel the library enqueues is bracketed by two HIP events
+ * on the stream it is launched on.  Process wide: not for concurrent use from
+ * several host threads.  fb_profile_enable(1) clears earlier records. */
+int fb_profile_enable(int on);
+
+/* Waits for the recorded events and writes a JSON array, one object per
+ * kernel in first-launch order: {"kernel", "launches", "total_ms", "avg_ms",
+ * "bytes_per_launch"} (bytes_per_launch = the algorithmic bytes: one read and
+ * one write of the grid for a pass).  Returns the length or a negative
+ * fb_status. */
+int fb_profile_report(char *buf, int cap);
 
 #ifdef __cplusplus
 }

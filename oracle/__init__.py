@@ -44,11 +44,12 @@ def _load():
     lib.orc_describe.argtypes = [i64, i64, i64, ctypes.c_char_p, i32]
     lib.orc_omega.argtypes = [i64, i64, i32, dp, dp]
     lib.orc_fft3d.argtypes = [i64, i64, i64, i32, dp]
+    lib.orc_fft3d_axes.argtypes = [i64, i64, i64, i32, i32, dp]
     lib.orc_fft1d_many.argtypes = [i64, i64, i32, dp]
     lib.orc_dft3d_brute.argtypes = [i64, i64, i64, i32, dp, dp]
     lib.orc_evolve.argtypes = [i64, i64, i64, dp, ctypes.c_double, ctypes.c_double]
     lib.orc_checksum.argtypes = [i64, i64, i64, dp, dp]
-    for f in ("orc_radices", "orc_describe", "orc_fft3d", "orc_fft1d_many", "orc_dft3d_brute",
+    for f in ("orc_radices", "orc_describe", "orc_fft3d", "orc_fft3d_axes", "orc_fft1d_many", "orc_dft3d_brute",
               "orc_evolve", "orc_checksum"):
         getattr(lib, f).restype = i32
     _lib = lib
@@ -98,6 +99,16 @@ def fft3d(x, sign: int = -1) -> np.ndarray:
     rc = _load().orc_fft3d(nx, ny, nz, sign, _dp(a))
     if rc:
         raise ValueError(f"orc_fft3d failed ({rc})")
+    return a
+
+
+def fft3d_axes(x, sign: int, axes: int) -> np.ndarray:
+    """Transform along the axes selected by the mask (bit 0 z, bit 1 y, bit 2 x)."""
+    a = _as_grid(x).copy()
+    nx, ny, nz = a.shape
+    rc = _load().orc_fft3d_axes(nx, ny, nz, sign, axes, _dp(a))
+    if rc:
+        raise ValueError(f"orc_fft3d_axes failed ({rc})")
     return a
 
 

@@ -251,28 +251,46 @@ static int fft_axis(double *data, int64_t n, int64_t stride, int64_t count, int6
     return err ? -1 : 0;
 }
 
-/* In-place 3D transform: z, then y, then x.  sign -1 forward (unscaled),
- * sign +1 inverse divided by N = nx ny nz after the last axis. */
-int orc_fft3d(int64_t nx, int64_t ny, int64_t nz, int sign, double *data)
+/* In-place transform along the axes selected by `axes` (bit 0 z, bit 1 y,
+ * bit 2 x), in the order z, y, x.  sign -1 forward (unscaled), sign +1
+ * inverse divided by the product of the selected lengths. */
+int orc_fft3d_axes(int64_t nx, int64_t ny, int64_t nz, int sign, int axes, double *data)
 {
-    if (nx < 1 || ny < 1 || nz < 1 || (sign != 1 && sign != -1)) return -1;
+    if (nx < 1 || ny < 1 || nz < 1 || (sign != 1 && sign != -1) || axes < 0 || axes > 7) return -1;
     int r[ORC_MAX_RADICES];
     if (orc_radices(nx, r, ORC_MAX_RADICES) < 0 || orc_radices(ny, r, ORC_MAX_RADICES) < 0 ||
         orc_radices(nz, r, ORC_MAX_RADICES) < 0)
         return -2;
+    int64_t nsel = 1;
     /* z: pencils (x, y), contiguous */
-    if (fft_axis(data, nz, 1, nx * ny, 1, 0, nz, sign)) return -3;
+    if (axes & 1) {
+        if (fft_axis(data, nz, 1, nx * ny, 1, 0, nz, sign)) return -3;
+        nsel *= nz;
+    }
     /* y: pencils (x, z), stride nz */
-    if (fft_axis(data, ny, nz, nx * nz, nz, 1, ny * nz, sign)) return -3;
+    if (axes & 2) {
+        if (fft_axis(data, ny, nz, nx * nz, nz, 1, ny * nz, sign)) return -3;
+        nsel *= ny;
+    }
     /* x: pencils (y, z), stride ny nz */
-    if (fft_axis(data, nx, ny * nz, ny * nz, ny * nz, 1, 0, sign)) return -3;
+    if (axes & 4) {
+        if (fft_axis(data, nx, ny * nz, ny * nz, ny * nz, 1, 0, sign)) return -3;
+        nsel *= nx;
+    }
     if (sign > 0) {
-        const double N = (double)(nx * ny * nz);
+        const double N = (double)nsel;
         const int64_t tot = 2 * nx * ny * nz;
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < tot; i++) data[i] = data[i] / N;
     }
     return 0;
+}
+
+/* In-place 3D transform: z, then y, then x.  sign -1 forward (unscaled),
+ * sign +1 inverse divided by N = nx ny nz after the last axis. */
+int orc_fft3d(int64_t nx, int64_t ny, int64_t nz, int sign, double *data)
+{
+    return orc_fft3d_axes(nx, ny, nz, sign, 7, data);
 }
 
 /* `howmany` contiguous 1D transforms of length n (unscaled for sign -1,

@@ -13,7 +13,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "fb.h"
 #include "fb_internal.hpp"
@@ -51,6 +53,54 @@ int hip_fail(hipError_t e, const char *what)
 }
 
 int esize_of(int dtype) { return dtype == FB_C128 ? 16 : 8; }
+
+// ---- optional per-launch timing (process wide, for benchmarks)
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t pool_event()
+{
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void prof_clear_locked()
+{
+    for (auto &r : g_prof) {
+        g_event_pool.push_back(r.a);
+        g_event_pool.push_back(r.b);
+    }
+    g_prof.clear();
+}
+
+// Runs launch(); when timing is on, brackets it with two events on `st`.
+template <class F> hipError_t timed_launch(const char *name, double bytes, hipStream_t st, F &&launch)
+{
+    if (!g_prof_on) return launch();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    hipEvent_t a = pool_event(), b = pool_event();
+    if (!a || !b) return launch();
+    (void)hipEventRecord(a, st);
+    hipError_t e = launch();
+    (void)hipEventRecord(b, st);
+    g_prof.push_back({name, a, b, bytes});
+    return e;
+}
+
+const char *dtype_tag(int esize) { return esize == 16 ? "c128" : "c64"; }
 
 // Axis geometry: index 0 = z (contiguous), 1 = y, 2 = x.
 struct AxisPlan {
@@ -203,7 +253,11 @@ int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, dou
         args.ev_la = ev->ev_la;
         args.ev_lb = ev->ev_lb;
     }
-    hipError_t e = A.pass.launch(args, st);
+    char name[96];
+    snprintf(name, sizeof name, "fft_pass<%s,n=%lld,%s%s>", dtype_tag(p->esize), (long long)A.n,
+             A.contig ? "contiguous" : "strided", ev ? ",evolve" : "");
+    const double bytes = 2.0 * (double)p->N * (double)p->esize;
+    hipError_t e = timed_launch(name, bytes, st, [&] { return A.pass.launch(args, st); });
     if (e != hipSuccess) return hip_fail(e, "pass launch");
     return FB_OK;
 }
@@ -211,22 +265,27 @@ int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, dou
 // Runs the active passes z, y, x.  The first active pass reads `in`; later
 // ones work in place on `out`.  `ev` (optional) fuses the evolution into the
 // first pass, which must then be the contiguous z pass.
-int run_passes(const fb_plan *p, const void *in, void *out, int dir, const PassArgs *ev, hipStream_t st)
+int run_passes(const fb_plan *p, const void *in, void *out, int dir, const PassArgs *ev, hipStream_t st,
+               int axes = 7)
 {
     int last = -1;
+    double nsel = 1.0;
     for (int a = 0; a < 3; a++)
-        if (p->ax[a].n > 1) last = a;
+        if ((axes >> a & 1) && p->ax[a].n > 1) {
+            last = a;
+            nsel *= (double)p->ax[a].n;
+        }
     if (last < 0) {
         if (in != out) {
-            hipError_t e = hipMemcpyAsync(out, in, (size_t)p->esize, hipMemcpyDeviceToDevice, st);
+            hipError_t e = hipMemcpyAsync(out, in, (size_t)p->N * (size_t)p->esize, hipMemcpyDeviceToDevice, st);
             if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
         }
         return FB_OK;
     }
     bool first = true;
     for (int a = 0; a < 3; a++) {
-        if (p->ax[a].n <= 1) continue;
-        const double scale = (dir > 0 && a == last) ? 1.0 / (double)p->N : 1.0;
+        if (!(axes >> a & 1) || p->ax[a].n <= 1) continue;
+        const double scale = (dir > 0 && a == last) ? 1.0 / nsel : 1.0;
         int rc = launch_axis(p, a, first ? in : out, out, dir > 0, scale, first ? ev : nullptr, st);
         if (rc) return rc;
         first = false;
@@ -369,11 +428,71 @@ fb_status fb_fft3d_exec(const fb_plan *p, const void *in, void *out, int dir, vo
     return (fb_status)ok();
 }
 
+fb_status fb_fft3d_exec_axes(const fb_plan *p, const void *in, void *out, int dir, int axes, void *hip_stream)
+{
+    if (check_plan(p) || check_grid_ptr(p, in, "in") || check_grid_ptr(p, out, "out")) return (fb_status)g_code;
+    if (dir != FB_FORWARD && dir != FB_INVERSE)
+        return (fb_status)fail(FB_ERR_INVALID_ARG, "dir must be FB_FORWARD (-1) or FB_INVERSE (+1), got %d", dir);
+    if (axes < 0 || axes > 7) return (fb_status)fail(FB_ERR_INVALID_ARG, "axes must be a mask of bits 0 (z), 1 (y), 2 (x)");
+    if (check_no_partial_overlap(p, in, out, true, "fb_fft3d_exec_axes")) return (fb_status)g_code;
+    if (check_device(p)) return (fb_status)g_code;
+    if (run_passes(p, in, out, dir, nullptr, (hipStream_t)hip_stream, axes)) return (fb_status)g_code;
+    return (fb_status)ok();
+}
+
+int fb_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_clear_locked();
+    g_prof_on = on != 0;
+    return ok();
+}
+
+int fb_profile_report(char *buf, int cap)
+{
+    if (!buf || cap <= 0) return fail(FB_ERR_INVALID_ARG, "buf is NULL or cap <= 0");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    struct Agg {
+        std::string name;
+        long n;
+        double ms, bytes;
+    };
+    std::vector<Agg> agg;
+    for (auto &r : g_prof) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        size_t i = 0;
+        while (i < agg.size() && agg[i].name != r.name) i++;
+        if (i == agg.size()) agg.push_back({r.name, 0, 0.0, r.bytes});
+        agg[i].n++;
+        agg[i].ms += ms;
+    }
+    std::string js = "[";
+    for (size_t i = 0; i < agg.size(); i++) {
+        char line[256];
+        snprintf(line, sizeof line, "%s{\"kernel\": \"%s\", \"launches\": %ld, \"total_ms\": %.6f, \"avg_ms\": %.6f, "
+                 "\"bytes_per_launch\": %.0f}", i ? ", " : "", agg[i].name.c_str(), agg[i].n, agg[i].ms,
+                 agg[i].ms / (double)agg[i].n, agg[i].bytes);
+        js += line;
+    }
+    js += "]";
+    if ((int)js.size() + 1 > cap) return fail(FB_ERR_INVALID_ARG, "buffer too small (%d bytes needed)", (int)js.size() + 1);
+    memcpy(buf, js.c_str(), js.size() + 1);
+    ok();
+    return (int)js.size();
+}
+
 fb_status fb_spectral_evolve(const fb_plan *p, void *u, double alpha, double t, void *hip_stream)
 {
     if (check_plan(p) || check_grid_ptr(p, u, "u") || check_alpha_t(alpha, t)) return (fb_status)g_code;
     if (check_device(p)) return (fb_status)g_code;
-    hipError_t e = fb::launch_evolve(p->esize, u, u, p->nx, p->ny, p->nz, evolve_c(alpha, t), (hipStream_t)hip_stream);
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = timed_launch(p->esize == 16 ? "evolve<c128>" : "evolve<c64>", 2.0 * p->N * p->esize, st, [&] {
+        return fb::launch_evolve(p->esize, u, u, p->nx, p->ny, p->nz, evolve_c(alpha, t), st);
+    });
     if (e != hipSuccess) return (fb_status)hip_fail(e, "evolve launch");
     return (fb_status)ok();
 }
@@ -383,7 +502,9 @@ fb_status fb_checksum(const fb_plan *p, const void *x, double *out2_dev, void *h
     if (check_plan(p) || check_grid_ptr(p, x, "x")) return (fb_status)g_code;
     if (!out2_dev || (uintptr_t)out2_dev % 8) return (fb_status)fail(FB_ERR_INVALID_ARG, "out2_dev is NULL or misaligned");
     if (check_device(p)) return (fb_status)g_code;
-    hipError_t e = fb::launch_checksum(p->esize, x, p->N, out2_dev, (hipStream_t)hip_stream);
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = timed_launch(p->esize == 16 ? "checksum<c128>" : "checksum<c64>", 1024.0 * p->esize + 16, st,
+                                [&] { return fb::launch_checksum(p->esize, x, p->N, out2_dev, st); });
     if (e != hipSuccess) return (fb_status)hip_fail(e, "checksum launch");
     return (fb_status)ok();
 }
@@ -408,12 +529,14 @@ fb_status fb_spectral_step(const fb_plan *p, const void *uhat0, void *x_out, dou
         ev.ev_lb = (int)p->ny;
         if (run_passes(p, uhat0, x_out, FB_INVERSE, &ev, st)) return (fb_status)g_code;
     } else {
-        hipError_t e = fb::launch_evolve(p->esize, uhat0, x_out, p->nx, p->ny, p->nz, c, st);
+        hipError_t e = timed_launch(p->esize == 16 ? "evolve<c128>" : "evolve<c64>", 2.0 * p->N * p->esize, st,
+                                    [&] { return fb::launch_evolve(p->esize, uhat0, x_out, p->nx, p->ny, p->nz, c, st); });
         if (e != hipSuccess) return (fb_status)hip_fail(e, "evolve launch");
         if (run_passes(p, x_out, x_out, FB_INVERSE, nullptr, st)) return (fb_status)g_code;
     }
     if (out2_dev) {
-        hipError_t e = fb::launch_checksum(p->esize, x_out, p->N, out2_dev, st);
+        hipError_t e = timed_launch(p->esize == 16 ? "checksum<c128>" : "checksum<c64>", 1024.0 * p->esize + 16, st,
+                                    [&] { return fb::launch_checksum(p->esize, x_out, p->N, out2_dev, st); });
         if (e != hipSuccess) return (fb_status)hip_fail(e, "checksum launch");
     }
     return (fb_status)ok();

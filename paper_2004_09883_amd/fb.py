@@ -31,7 +31,8 @@ DTYPE_NAMES = {FB_C128: "c128", FB_C64: "c64", FB_C64_SPLITBF16: "c64_splitbf16"
 # every entry point declared in include/fb.h
 EXPORTS = ("fb_version", "fb_last_error", "fb_describe_shape", "fb_fft3d_plan", "fb_fft3d_destroy",
            "fb_plan_device_bytes", "fb_plan_describe", "fb_fft3d_exec", "fb_spectral_evolve",
-           "fb_checksum", "fb_spectral_step", "fb_fill_uniform")
+           "fb_checksum", "fb_spectral_step", "fb_fill_uniform", "fb_fft3d_exec_axes",
+           "fb_profile_enable", "fb_profile_report")
 
 
 class FbError(RuntimeError):
@@ -67,6 +68,9 @@ def load():
         "fb_checksum": (i32, [vp, vp, vp, vp]),
         "fb_spectral_step": (i32, [vp, vp, vp, dbl, dbl, vp, vp]),
         "fb_fill_uniform": (i32, [vp, vp, ctypes.c_uint64, vp]),
+        "fb_fft3d_exec_axes": (i32, [vp, vp, vp, i32, i32, vp]),
+        "fb_profile_enable": (i32, [i32]),
+        "fb_profile_report": (i32, [ctypes.c_char_p, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -179,6 +183,26 @@ def fb_fft3d_exec(plan: Plan, x_in, x_out, direction: int = FB_FORWARD, stream=N
     plan.check_tensor(x_in, "in")
     plan.check_tensor(x_out, "out")
     _check(load().fb_fft3d_exec(plan.handle, _ptr(x_in), _ptr(x_out), direction, _stream(stream)))
+
+
+def fb_fft3d_exec_axes(plan: Plan, x_in, x_out, direction: int, axes: int, stream=None):
+    """Transform along the axes selected by the mask (bit 0 z, bit 1 y, bit 2 x)."""
+    plan.check_tensor(x_in, "in")
+    plan.check_tensor(x_out, "out")
+    _check(load().fb_fft3d_exec_axes(plan.handle, _ptr(x_in), _ptr(x_out), direction, axes, _stream(stream)))
+
+
+def fb_profile_enable(on: bool = True):
+    _check(load().fb_profile_enable(1 if on else 0))
+
+
+def fb_profile_report() -> list:
+    """Per-kernel timing recorded since fb_profile_enable(True)."""
+    import json
+    cap = 1 << 16
+    buf = ctypes.create_string_buffer(cap)
+    _check(load().fb_profile_report(buf, cap))
+    return json.loads(buf.value.decode())
 
 
 def fb_spectral_evolve(plan: Plan, u, alpha: float, t: float, stream=None):

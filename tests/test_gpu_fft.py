@@ -245,3 +245,34 @@ def test_partial_overlap_rejected():
     assert rc == fb.FB_ERR_INVALID_ARG
     rc = lib.fb_fft3d_exec(plan.handle, buf.data_ptr() + 8, buf.data_ptr(), -1, None)
     assert rc == fb.FB_ERR_INVALID_ARG   # misaligned
+
+
+@pytest.mark.parametrize("dtype", [fb.FB_C128, fb.FB_C64])
+@pytest.mark.parametrize("axes", range(8))
+def test_exec_axes(axes, dtype):
+    shape = (12, 16, 24)
+    x = inputs.uniform_grid(shape, 30 + axes)
+    plan = fb.Plan(*shape, dtype)
+    for direction in (fb.FB_FORWARD, fb.FB_INVERSE):
+        xin = dev(x, dtype)
+        out = torch.empty_like(xin)
+        fb.fb_fft3d_exec_axes(plan, xin, out, direction, axes)
+        ref = oracle.fft3d_axes(as_seen(x, dtype), direction, axes)
+        assert rel_l2(host(out), ref) < TOL[dtype], (axes, direction)
+
+
+def test_profile_hook_records_every_launch():
+    shape = (32, 32, 32)
+    plan = fb.Plan(*shape, fb.FB_C128)
+    x = torch.zeros(shape, dtype=torch.complex128, device="cuda")
+    fb.fb_profile_enable(True)
+    fb.fb_fft3d_exec(plan, x, x, fb.FB_FORWARD)
+    fb.fb_spectral_step(plan, x, torch.empty_like(x), 1e-6, 1.0, torch.zeros(2, dtype=torch.float64, device="cuda"))
+    rep = fb.fb_profile_report()
+    fb.fb_profile_enable(False)
+    names = [r["kernel"] for r in rep]
+    assert "fft_pass<c128,n=32,contiguous>" in names
+    assert "fft_pass<c128,n=32,contiguous,evolve>" in names
+    assert "checksum<c128>" in names
+    assert sum(r["launches"] for r in rep) == 3 + 3 + 1
+    assert all(r["avg_ms"] > 0 for r in rep)

@@ -192,6 +192,25 @@ def test_long_1d_vs_pocketfft(n):
     assert rel_l2(oracle.fft1d_many(x), np.fft.fft(x, axis=-1)) < 1e-13
 
 
+@pytest.mark.parametrize("axes", range(8))
+def test_axes_subset_vs_dft_matrix(axes):
+    """A transform along a subset of axes is the DFT along those axes only
+    (numpy DFT matrices applied per selected axis)."""
+    shape = (6, 8, 12)
+    x = inputs.uniform_grid(shape, 17)
+    for sign in (-1, +1):
+        ref = x.copy()
+        nsel = 1
+        for bit, ax in ((1, 2), (2, 1), (4, 0)):
+            if axes & bit:
+                ref = np.moveaxis(np.tensordot(dft_matrix(shape[ax], sign), ref, axes=([1], [ax])), 0, ax)
+                nsel *= shape[ax]
+        if sign > 0:
+            ref = ref / nsel
+        got = oracle.fft3d_axes(x, sign, axes)
+        assert rel_l2(got, ref) < 1e-14, (axes, sign)
+
+
 # ---------------------------------------------------------------- closed forms
 
 def test_delta_at_origin_is_all_ones():
