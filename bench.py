@@ -91,7 +91,8 @@ def forms_section(torch, fb, reps: int = 20) -> dict:
     shape = (512, 256, 256)
     n = math.prod(shape)
     out = {}
-    for name, dt, esize in (("c128", fb.FB_C128, 16), ("c64", fb.FB_C64, 8)):
+    for name, dt, esize in (("c128", fb.FB_C128, 16), ("c64", fb.FB_C64, 8),
+                            ("c64_splitbf16", fb.FB_C64_SPLITBF16, 8)):
         plan = fb.Plan(*shape, dt)
         x = torch.empty(shape, dtype=plan.torch_dtype, device="cuda")
         y = torch.empty_like(x)
@@ -113,6 +114,7 @@ def forms_section(torch, fb, reps: int = 20) -> dict:
         del x, y, plan
         torch.cuda.empty_cache()
     out["c64_speedup_vs_c128"] = round(out["c128"]["forward_ms"] / out["c64"]["forward_ms"], 3)
+    out["c64_splitbf16_speedup_vs_c128"] = round(out["c128"]["forward_ms"] / out["c64_splitbf16"]["forward_ms"], 3)
     out["workload"] = "forward 3D FFT of a 512x256x256 grid, 3 pencil passes"
     return out
 

@@ -128,7 +128,7 @@ int check_shape(int64_t nx, int64_t ny, int64_t nz, int dtype)
     return FB_OK;
 }
 
-void build_axes(int64_t nx, int64_t ny, int64_t nz, int esize, AxisPlan ax[3])
+void build_axes(int64_t nx, int64_t ny, int64_t nz, int esize, bool mx, AxisPlan ax[3])
 {
     const int64_t len[3] = {nz, ny, nx};
     size_t off = 0;
@@ -137,7 +137,7 @@ void build_axes(int64_t nx, int64_t ny, int64_t nz, int esize, AxisPlan ax[3])
         A.n = len[a];
         A.rp = fb::radix_plan((int)A.n);
         A.contig = (a == 0);
-        A.pass = A.n > 1 ? fb::find_pass(esize, (int)A.n, A.contig) : PassInfo{nullptr, 0, 0};
+        A.pass = A.n > 1 ? fb::find_pass(esize, (int)A.n, A.contig, mx) : PassInfo{nullptr, 0, 0, 0};
         A.tw_off = off;
         off += (size_t)A.rp.twlen;
     }
@@ -254,8 +254,8 @@ int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, dou
         args.ev_lb = ev->ev_lb;
     }
     char name[96];
-    snprintf(name, sizeof name, "fft_pass<%s,n=%lld,%s%s>", dtype_tag(p->esize), (long long)A.n,
-             A.contig ? "contiguous" : "strided", ev ? ",evolve" : "");
+    snprintf(name, sizeof name, "fft_pass<%s,n=%lld,%s%s%s>", dtype_tag(p->esize), (long long)A.n,
+             A.contig ? "contiguous" : "strided", A.pass.mx ? ",mfma" : "", ev ? ",evolve" : "");
     const double bytes = 2.0 * (double)p->N * (double)p->esize;
     hipError_t e = timed_launch(name, bytes, st, [&] { return A.pass.launch(args, st); });
     if (e != hipSuccess) return hip_fail(e, "pass launch");
@@ -323,7 +323,7 @@ int fb_describe_shape(int64_t nx, int64_t ny, int64_t nz, int dtype, char *buf, 
     if (check_shape(nx, ny, nz, dtype)) return g_code;
     if (!buf || cap <= 0) return fail(FB_ERR_INVALID_ARG, "buf is NULL or cap <= 0");
     AxisPlan ax[3];
-    build_axes(nx, ny, nz, esize_of(dtype), ax);
+    build_axes(nx, ny, nz, esize_of(dtype), dtype == FB_C64_SPLITBF16, ax);
     char tmp[256];
     describe(ax, tmp, sizeof tmp);
     const int len = (int)strlen(tmp);
@@ -344,7 +344,7 @@ fb_plan *fb_fft3d_plan(int64_t nx, int64_t ny, int64_t nz, int dtype)
     p->nx = nx; p->ny = ny; p->nz = nz; p->N = nx * ny * nz;
     p->dtype = dtype;
     p->esize = esize_of(dtype);
-    build_axes(nx, ny, nz, p->esize, p->ax);
+    build_axes(nx, ny, nz, p->esize, dtype == FB_C64_SPLITBF16, p->ax);
     for (int a = 0; a < 3; a++) {
         if (p->ax[a].n > 1 && !p->ax[a].pass.launch) {
             fail(FB_ERR_UNSUPPORTED_SIZE, "no pass for length %lld", (long long)p->ax[a].n);

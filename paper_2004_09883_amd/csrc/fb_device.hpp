@@ -131,6 +131,9 @@ template <int R, typename V> __device__ __forceinline__ void dft(V *a)
     else static_assert(R == 2, "unsupported radix");
 }
 
+// Padded LDS position of element i of a pencil row: one pad slot every 16.
+__device__ __forceinline__ int lds_pos(int i) { return i + (i >> 4); }
+
 // exp(-c k2): binary64 for complex128 grids, binary32 for complex64 grids.
 template <typename R> __device__ __forceinline__ R evol_factor(double c, double k2)
 {

@@ -33,11 +33,14 @@ struct PassInfo {
     PassLauncher launch;
     int pencils_per_wg;
     int threads;
+    int mx;   // 1 when the radix-16 stages run on the matrix cores
 };
 
-// esize: 16 (complex128) or 8 (complex64).  Returns launch == nullptr when
-// the length has no instantiated pass.
-PassInfo find_pass(int esize, int n, bool contig);
+// esize: 16 (complex128) or 8 (complex64); mx asks for the matrix-core
+// radix-16 variant (complex64 only; the vector-unit pass is returned where
+// no such variant exists).  Returns launch == nullptr when the length has no
+// instantiated pass.
+PassInfo find_pass(int esize, int n, bool contig, bool mx);
 
 // Twiddle tables of one axis: for each stage s with ns > 1, entry
 // off[s] + (q-1) ns + k = w_{ns r}^(q k), w_L = exp(-2 pi i / L), in binary64

@@ -1,0 +1,147 @@
+// fb_mfma.hpp -- radix-16 DFT stages on the gfx950 matrix cores with
+// split-bf16 operands and fp32 accumulation.
+//
+// A radix-16 DFT of 16 complex values is the real product
+//     [Yr; Yi] = [[Wr, -Wi], [Wi, Wr]] [xr; xi],   W[k][q] = w16^(k q),
+// a 32 x 32 matrix times a 32-vector.  Sixteen such butterflies form one
+// 16 x 16 x 32 matrix product per output half (Yr rows, Yi rows):
+// v_mfma_f32_16x16x32_bf16 with A = 16 rows of the DFT matrix (K = 32 real
+// inputs) and B = 16 butterflies (columns).
+//
+// Precision: every data value x is split x = hi + lo with hi = bf16(x),
+// lo = bf16(x - hi) (round to nearest even); every matrix entry
+// w = whi + wlo + wlo2 likewise in three terms.  The products kept are
+//     wlo2 hi + wlo lo + wlo hi + whi lo + whi hi
+// (smallest first), accumulated in fp32; the dropped terms are below
+// 2^-24 relative, and the representation error of x (below 2^-16) dominates.
+//
+// Operand layout of the 16x16x32 instruction (64 lanes, lane = c + 16 g):
+//   A: lane holds row (lane % 16), K elements 8 g .. 8 g + 7
+//   B: lane holds column (lane % 16), K elements 8 g .. 8 g + 7
+//   D: lane holds rows 4 g .. 4 g + 3 of column (lane % 16)
+// The K index is assigned here as K = 8 g + 2 i + p <-> (element q = 4 g + i,
+// part p: 0 real, 1 imaginary), the same for A and B, so lane (c, g) of a
+// butterfly group supplies its complex inputs q = 4g..4g+3 and receives its
+// complex outputs k = 4g..4g+3.
+#pragma once
+#include "fb_device.hpp"
+
+namespace fb {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float cos16(int m)
+{
+    constexpr double c[16] = {1.0, K::C8, K::R2, K::S8, 0.0, -K::S8, -K::R2, -K::C8,
+                              -1.0, -K::C8, -K::R2, -K::S8, 0.0, K::S8, K::R2, K::C8};
+    return (float)c[m & 15];
+}
+// sin(2 pi m / 16) = cos(2 pi (m - 4) / 16)
+__device__ __forceinline__ float sin16(int m) { return cos16(m - 4); }
+
+// The DFT matrix rows this lane supplies, split into three bf16 terms.
+struct MxConsts {
+    bf16x8 ar[3];  // rows of Yr: [Wr, -Wi]
+    bf16x8 ai[3];  // rows of Yi: [Wi,  Wr]
+};
+
+__device__ __forceinline__ void split3(float v, __bf16 &a, __bf16 &b, __bf16 &c)
+{
+    a = (__bf16)v;
+    const float r1 = v - (float)a;
+    b = (__bf16)r1;
+    c = (__bf16)(r1 - (float)b);
+}
+
+__device__ __forceinline__ MxConsts mx_consts(int lane)
+{
+    MxConsts cs;
+    const int kout = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int i = e >> 1, p = e & 1, q = 4 * g + i;
+        const int m = (kout * q) & 15;
+        const float wr = cos16(m), wi = -sin16(m);   // W = wr + i wi (forward)
+        const float vr = p ? -wi : wr;
+        const float vi = p ? wr : wi;
+        __bf16 h, l, l2;
+        split3(vr, h, l, l2);
+        cs.ar[0][e] = h; cs.ar[1][e] = l; cs.ar[2][e] = l2;
+        split3(vi, h, l, l2);
+        cs.ai[0][e] = h; cs.ai[1][e] = l; cs.ai[2][e] = l2;
+    }
+    return cs;
+}
+
+__device__ __forceinline__ f32x4 mx_dot(const bf16x8 *w, bf16x8 xh, bf16x8 xl)
+{
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[2], xh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[1], xl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[1], xh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0], xl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0], xh, acc, 0, 0, 0);
+    return acc;
+}
+
+// One radix-16 stage of a pass on the matrix cores, LDS to LDS.
+//
+// The workgroup's pencil rows live in LDS (`lds`, row stride LS, padded
+// positions); the stage input q of butterfly b of pencil pp is
+// row[pp][b + q N/16].  Wave w takes the four groups 4w .. 4w+3 of 16
+// butterflies (butterfly beta = 16 group + lane%16, pencil beta / (N/16),
+// b = beta % (N/16)); the workgroup has exactly P N / 16 threads, so the
+// groups cover every butterfly once.  Inputs are read and twiddled first;
+// after a barrier the outputs are written to their Stockham positions
+// (b div Ns) Ns 16 + (b mod Ns) + k Ns; a second barrier ends the stage.
+template <int N, int LS, int Ns, int TWOFF>
+__device__ __forceinline__ void mx_stage16(float2 *lds, const float2 *__restrict__ tw, const MxConsts &A,
+                                           int wave, int lane)
+{
+    constexpr int NBF = N / 16;
+    const int c = lane & 15, g = lane >> 4;
+    float2 x[4][4];
+    int rowoff[4], bb[4];
+#pragma unroll
+    for (int gi = 0; gi < 4; gi++) {
+        const int beta = 16 * (4 * wave + gi) + c;
+        const int pp = beta / NBF, b = beta % NBF;
+        rowoff[gi] = pp * LS;
+        bb[gi] = b;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int q = 4 * g + i;
+            float2 v = lds[rowoff[gi] + lds_pos(b + q * NBF)];
+            if constexpr (Ns > 1) {
+                if (q > 0) v = cmul(v, tw[TWOFF + (q - 1) * Ns + (b % Ns)]);
+            }
+            x[gi][i] = v;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int gi = 0; gi < 4; gi++) {
+        bf16x8 xh, xl;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const __bf16 hr = (__bf16)x[gi][i].x, hi = (__bf16)x[gi][i].y;
+            xh[2 * i] = hr;
+            xh[2 * i + 1] = hi;
+            xl[2 * i] = (__bf16)(x[gi][i].x - (float)hr);
+            xl[2 * i + 1] = (__bf16)(x[gi][i].y - (float)hi);
+        }
+        const f32x4 yr = mx_dot(A.ar, xh, xl);
+        const f32x4 yi = mx_dot(A.ai, xh, xl);
+        const int b = bb[gi];
+        const int idx = (b / Ns) * Ns * 16 + (b % Ns);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int k = 4 * g + e;
+            lds[rowoff[gi] + lds_pos(idx + k * Ns)] = make_float2(yr[e], yi[e]);
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace fb

@@ -8,14 +8,14 @@
 
 namespace fb {
 
-PassInfo find_pass_c128(int n, bool contig);
-PassInfo find_pass_c64(int n, bool contig);
+PassInfo find_pass_c128(int n, bool contig, bool mx);
+PassInfo find_pass_c64(int n, bool contig, bool mx);
 
-PassInfo find_pass(int esize, int n, bool contig)
+PassInfo find_pass(int esize, int n, bool contig, bool mx)
 {
-    if (esize == 16) return find_pass_c128(n, contig);
-    if (esize == 8) return find_pass_c64(n, contig);
-    return {nullptr, 0, 0};
+    if (esize == 16) return find_pass_c128(n, contig, false);
+    if (esize == 8) return find_pass_c64(n, contig, mx);
+    return {nullptr, 0, 0, 0};
 }
 
 // ---------------------------------------------------------------- twiddles

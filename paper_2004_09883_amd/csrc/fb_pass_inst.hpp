@@ -7,32 +7,42 @@
 
 namespace fb {
 
-template <typename V, int N, bool CONTIG> hipError_t launch_pass(const PassArgs &a, hipStream_t st)
+template <typename V, int N, bool CONTIG, bool MX> hipError_t launch_pass(const PassArgs &a, hipStream_t st)
 {
     using Cfg = PassCfg<V, N, CONTIG>;
     const int64_t blocks = (a.npencils + Cfg::P - 1) / Cfg::P;
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((fft_pass<V, N, CONTIG>), dim3((unsigned)blocks), dim3(Cfg::THREADS), 0, st, a);
+    hipLaunchKernelGGL((fft_pass<V, N, CONTIG, MX>), dim3((unsigned)blocks), dim3(Cfg::THREADS), 0, st, a);
     return hipGetLastError();
 }
 
-template <typename V, int N> PassInfo pass_info(bool contig)
+// MX selects the matrix-core radix-16 variant where one exists (complex64);
+// otherwise the vector-unit pass is returned.
+template <typename V, int N, bool CONTIG> PassInfo pass_info_k(bool mx)
 {
-    if (contig) return {&launch_pass<V, N, true>, PassCfg<V, N, true>::P, PassCfg<V, N, true>::THREADS};
-    return {&launch_pass<V, N, false>, PassCfg<V, N, false>::P, PassCfg<V, N, false>::THREADS};
+    using Cfg = PassCfg<V, N, CONTIG>;
+    if constexpr (mx_capable<V, N, CONTIG>()) {
+        if (mx) return {&launch_pass<V, N, CONTIG, true>, Cfg::P, Cfg::THREADS, 1};
+    }
+    return {&launch_pass<V, N, CONTIG, false>, Cfg::P, Cfg::THREADS, 0};
+}
+
+template <typename V, int N> PassInfo pass_info(bool contig, bool mx)
+{
+    return contig ? pass_info_k<V, N, true>(mx) : pass_info_k<V, N, false>(mx);
 }
 
 #define FB_FOR_EACH_LENGTH(X) \
     X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) \
     X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096)
 
-template <typename V> PassInfo find_pass_t(int n, bool contig)
+template <typename V> PassInfo find_pass_t(int n, bool contig, bool mx)
 {
     switch (n) {
-#define FB_CASE(L) case L: return pass_info<V, L>(contig);
+#define FB_CASE(L) case L: return pass_info<V, L>(contig, mx);
         FB_FOR_EACH_LENGTH(FB_CASE)
 #undef FB_CASE
-    default: return {nullptr, 0, 0};
+    default: return {nullptr, 0, 0, 0};
     }
 }
 

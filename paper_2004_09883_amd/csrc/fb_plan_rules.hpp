@@ -77,16 +77,30 @@ constexpr int lds_pencil_stride(int n)
 
 constexpr int lds_budget_bytes(bool contig) { return contig ? 40 * 1024 : 72 * 1024; }
 
+constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
+
+constexpr bool pencils_fit(int P, int n, bool contig, int esize)
+{
+    return P * threads_per_pencil(n) <= 1024 && P * lds_pencil_stride(n) * esize <= lds_budget_bytes(contig);
+}
+
 // Pencils per workgroup.  Contiguous passes aim for 256 threads; strided
 // passes aim for 16 (c128) / 32 (c64) adjacent pencils so that every row
-// access is a 256-byte segment.  Both are capped by 1024 threads and by the
-// LDS budget.
+// access is a 256-byte segment.  P is then moved to a multiple of
+// 64 / gcd(T, 64) so that the workgroup is whole wavefronts, when that fits;
+// finally it is capped by 1024 threads and by the LDS budget.
 constexpr int pencils_per_wg(int n, bool contig, int esize)
 {
     const int T = threads_per_pencil(n);
     int P = contig ? (256 / T > 0 ? 256 / T : 1) : (esize == 16 ? 16 : 32);
     if (!contig && T == 1) P = 64;
-    while (P > 1 && (P * T > 1024 || P * lds_pencil_stride(n) * esize > lds_budget_bytes(contig))) P /= 2;
+    const int m = 64 / gcd_int(T, 64);
+    if (P % m) {
+        const int down = (P / m) * m, up = down + m;
+        if (down > 0) P = down;
+        else if (pencils_fit(up, n, contig, esize)) P = up;
+    }
+    while (P > 1 && !pencils_fit(P, n, contig, esize)) P /= 2;
     return P;
 }
 

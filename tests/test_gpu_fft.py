@@ -16,7 +16,8 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-TOL = {fb.FB_C128: 1e-12, fb.FB_C64: 1e-5}
+TOL = {fb.FB_C128: 1e-12, fb.FB_C64: 1e-5, fb.FB_C64_SPLITBF16: 1e-5}
+DTYPES = [fb.FB_C128, fb.FB_C64, fb.FB_C64_SPLITBF16]
 LENGTHS = [2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096]
 
 
@@ -67,7 +68,7 @@ def run_fft(shape, dtype, seed=1, direction=fb.FB_FORWARD, inplace=False):
 
 # ---------------------------------------------------------------- one axis at a time
 
-@pytest.mark.parametrize("dtype", [fb.FB_C128, fb.FB_C64])
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("n", LENGTHS)
 @pytest.mark.parametrize("axis", ["z", "y", "x"])
 def test_single_axis_pass(axis, n, dtype):
@@ -84,7 +85,7 @@ SHAPES_3D = [(64, 64, 64), (32, 48, 96), (12, 96, 24), (3, 6, 12), (1, 1, 1), (1
              (2, 4096, 1), (128, 256, 512), (256, 256, 128)]
 
 
-@pytest.mark.parametrize("dtype", [fb.FB_C128, fb.FB_C64])
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("shape", SHAPES_3D)
 def test_fft3d(shape, dtype):
     print(f"fft3d shape={shape} dtype={dtype}", flush=True)
@@ -214,9 +215,44 @@ def test_block_strong_decay_and_nz1_fallback():
     check_block((24, 12, 48), fb.FB_C128, seed=8, alpha=1e-3, steps=3)
 
 
-def test_block_c64():
-    check_block((64, 64, 64), fb.FB_C64, seed=1, alpha=1e-6, steps=6)
-    check_block((128, 64, 96), fb.FB_C64, seed=2, alpha=1e-6, steps=3, gaussian=True)
+@pytest.mark.parametrize("dtype", [fb.FB_C64, fb.FB_C64_SPLITBF16])
+def test_block_c64(dtype):
+    check_block((64, 64, 64), dtype, seed=1, alpha=1e-6, steps=6)
+    check_block((128, 64, 96), dtype, seed=2, alpha=1e-6, steps=3, gaussian=True)
+
+
+def test_precision_forms_512x256x256():
+    """The precision-form workload: 512 x 256 x 256, Gaussian N(0,1) input
+    (seed 2), 10 evolve steps with alpha = 1e-6; every form against the
+    binary64 oracle, every step."""
+    shape, alpha, steps = (512, 256, 256), 1e-6, 10
+    x0 = inputs.gaussian_grid(shape, 2)
+    refs = {}
+    for label, xs in (("exact", x0), ("c64", inputs.round_c64(x0).astype(np.complex128))):
+        X0 = oracle.fft3d(xs, -1)
+        refs[label] = X0
+    report = {}
+    for dtype in DTYPES:
+        plan = fb.Plan(*shape, dtype)
+        u0 = dev(x0, dtype)
+        fb.fb_fft3d_exec(plan, u0, u0, fb.FB_FORWARD)
+        xt = torch.empty_like(u0)
+        sums = torch.zeros((steps, 2), dtype=torch.float64, device="cuda")
+        X0 = refs["exact" if dtype == fb.FB_C128 else "c64"]
+        worst = 0.0
+        for t in range(1, steps + 1):
+            fb.fb_spectral_step(plan, u0, xt, alpha, t, sums[t - 1])
+            got = host(xt)
+            ref = oracle.fft3d(oracle.evolve(X0, alpha, t), +1)
+            e = rel_l2(got, ref)
+            worst = max(worst, e)
+            s = sums[t - 1].cpu().numpy()
+            assert e < TOL[dtype], (dtype, t, e)
+            assert checksum_err(complex(s[0], s[1]), ref) < TOL[dtype], (dtype, t)
+        report[fb.DTYPE_NAMES[dtype]] = worst
+        del u0, xt, plan
+        torch.cuda.empty_cache()
+    print("precision forms, worst rel L2 over 10 steps:", report, flush=True)
 
 
 def test_block_256x256x128_c128_20_steps():
