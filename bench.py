@@ -119,6 +119,90 @@ def forms_section(torch, fb, reps: int = 20) -> dict:
     return out
 
 
+def batched_section(torch, fb, reps: int = 10) -> dict:
+    """4096 1D complex64 transforms of lengths drawn from {2^k, 3*2^k : 8 <= k
+    <= 16} (seed 3) plus 64 2D 512 x 512 ones, uniform inputs: one persistent
+    launch versus one launch per (length, pass) group."""
+    from paper_2004_09883_amd import inputs
+
+    lens = inputs.batch_lengths(4096, 3).tolist()
+    batch = fb.Batch(lens, n2d=64, side2d=512)
+    x = torch.empty(batch.elements, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    ws = torch.empty(batch.workspace_bytes(False) + 256, dtype=torch.uint8, device="cuda")
+    wsp = (ws.data_ptr() + 255) // 256 * 256
+    xr = torch.from_numpy(inputs.uniform_grid((batch.elements,), 3).astype("complex64")).cuda()
+    x.copy_(xr)
+    del xr
+    flops = sum(5.0 * n * math.log2(n) for n in lens) + 64 * 5.0 * 512 * 512 * math.log2(512 * 512)
+    model_bytes = 0
+    for n in lens:
+        model_bytes += (2 if n <= 4096 else 4) * 8 * n
+    model_bytes += 64 * 4 * 8 * 512 * 512
+    out = {"workload": "4096 1D complex64 FFTs, lengths uniform over {2^k, 3*2^k: 8<=k<=16} (seed 3), plus 64 "
+                       "2D 512x512; uniform [-1,1) inputs", "transforms": 4096 + 64, "elements": batch.elements,
+           "model_bytes": model_bytes, "per_group_launches": batch.launches}
+    for mode, persistent in (("per_group_launches", False), ("persistent", True)):
+        for _ in range(2):
+            fb.fb_batch_exec(batch, x, y, wsp, fb.FB_FORWARD, persistent)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fb.fb_batch_exec(batch, x, y, wsp, fb.FB_FORWARD, persistent)
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / reps
+        out[mode] = {"ms": round(ms, 4), "gflops": round(flops / ms / 1e6, 1),
+                     "hbm_roofline_frac": round(model_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+    out["persistent_speedup"] = round(out["per_group_launches"]["ms"] / out["persistent"]["ms"], 3)
+    del x, y, ws, batch
+    torch.cuda.empty_cache()
+    return out
+
+
+PAPER_2D = (1, 2048, 2048)
+
+
+def paper_2d_section(torch, fb, reps: int = 10) -> dict:
+    """The paper's own Fourier-transform workload size (a 2048 x 2048 complex
+    grid, section 5.1(b)): forward 2D FFT on the device, alone and including
+    the host-to-device and device-to-host copies of the replaced-call framing."""
+    from paper_2004_09883_amd import inputs
+
+    out = {"workload": "forward 2D FFT of a 2048x2048 complex grid (the 3D plan with nx = 1)"}
+    for name, dt in (("c128", fb.FB_C128), ("c64", fb.FB_C64)):
+        plan = fb.Plan(*PAPER_2D, dt)
+        hx = torch.from_numpy(inputs.uniform_grid(PAPER_2D, 7)).to(plan.torch_dtype).pin_memory()
+        hy = torch.empty_like(hx).pin_memory()
+        x = torch.empty(PAPER_2D, dtype=plan.torch_dtype, device="cuda")
+        y = torch.empty_like(x)
+        x.copy_(hx)
+        for _ in range(3):
+            fb.fb_fft3d_exec(plan, x, y, fb.FB_FORWARD)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fb.fb_fft3d_exec(plan, x, y, fb.FB_FORWARD)
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / reps
+        s.record()
+        for _ in range(reps):
+            x.copy_(hx, non_blocking=True)
+            fb.fb_fft3d_exec(plan, x, y, fb.FB_FORWARD)
+            hy.copy_(y, non_blocking=True)
+        e.record()
+        torch.cuda.synchronize()
+        ms_copies = s.elapsed_time(e) / reps
+        out[name] = {"fft_ms": round(ms, 4), "with_copies_ms": round(ms_copies, 4),
+                     "gflops": round(5.0 * 2048 * 2048 * 22 / ms / 1e6, 1)}
+        del plan, x, y, hx, hy
+        torch.cuda.empty_cache()
+    return out
+
+
 def copy_reference(torch, nbytes: int = 1 << 29, reps: int = 20) -> dict:
     """A plain device-to-device copy (torch's copy kernel) of a grid-sized
     buffer: the practical bandwidth ceiling a streaming pass is compared with."""
@@ -148,6 +232,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a graph replay")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="measured duration of the serving run (0 skips it)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate of the serving run")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain 512 MiB copy (counter calibration)")
     args = ap.parse_args()
@@ -185,18 +273,38 @@ def main() -> int:
         step()
     torch.cuda.synchronize()
 
+    # per-kernel durations: the library brackets each of its launches with
+    # HIP events on the stream it launches on (eager launches)
     fb.fb_profile_enable(True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    t_wall = time.perf_counter()
     start.record()
     for _ in range(args.steps):
         step()
     stop.record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
     prof = fb.fb_profile_report()
     fb.fb_profile_enable(False)
+    eager_ms = start.elapsed_time(stop) / args.steps
+
+    # the timed region: the whole block captured once in a HIP graph and
+    # replayed, which removes the host launch gaps between its 83 kernels
+    graph = None
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for _ in range(args.warmup):
+            graph.replay()
+    run = graph.replay if graph is not None else step
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start.record()
+    for _ in range(args.steps):
+        run()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
 
     ms = start.elapsed_time(stop) / args.steps
     flops_step = (1 + T_STEPS) * flops_fft(SHAPE)
@@ -220,14 +328,34 @@ def main() -> int:
            "config": {"workload": "spectral block 256x256x128 complex128: forward 3D FFT + 20 x (evolve "
                                   "alpha=1e-6 + inverse 3D FFT + stride-17 checksum)",
                       "shape": list(SHAPE), "steps_per_block": T_STEPS, "alpha": ALPHA,
-                      "transforms_per_step": 1 + T_STEPS, "wall_s": round(wall, 3)},
+                      "transforms_per_step": 1 + T_STEPS, "wall_s": round(wall, 3),
+                      "launch": "hip graph (one replay per step)" if graph is not None else "eager",
+                      "eager_ms_per_step": round(eager_ms, 4)},
            "roofline": roofline,
            "kernels": [{k: v for k, v in p.items()} for p in prof]}
     if not args.no_forms:
         rec["forms_512x256x256"] = forms_section(torch, fb)
+        rec["batched"] = batched_section(torch, fb)
+        rec["paper_2d_2048"] = paper_2d_section(torch, fb)
         rec["copy_reference"] = copy_reference(torch)
+    if args.serve_seconds > 0:
+        from paper_2004_09883_amd import serve
+        rec["serving"] = serve.run_serving(rate=args.serve_rate, duration=args.serve_seconds, warmup=1.0)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline()
+        if "paper_2d_2048" in rec:
+            # the paper's unit: times faster than all-CPU processing, copies included
+            import oracle
+            from paper_2004_09883_amd import inputs
+            x = inputs.uniform_grid(PAPER_2D, 7)
+            t0 = time.perf_counter()
+            oracle.fft3d(x, -1)
+            cpu_ms = (time.perf_counter() - t0) * 1e3
+            p2 = rec["paper_2d_2048"]
+            p2["cpu_oracle_ms"] = round(cpu_ms, 2)
+            p2["cpu_oracle_threads"] = oracle.threads()
+            for k in ("c128", "c64"):
+                p2[k]["x_vs_cpu_with_copies"] = round(cpu_ms / p2[k]["with_copies_ms"], 1)
     print(json.dumps(rec), flush=True)
     return 0
 

@@ -134,6 +134,99 @@ fb_status fb_spectral_step(const fb_plan *p, const void *uhat0, void *x_out, dou
  * the binary64 values rounded to nearest). */
 fb_status fb_fill_uniform(const fb_plan *p, void *x, uint64_t seed, void *hip_stream);
 
+/* ---- Batched form ------------------------------------------------------
+ * Many independent complex64 transforms in one call: n1d 1D transforms of
+ * lengths lens[0..n1d) (each 2^a or 3*2^a, 2 <= n <= 2^21) and n2d 2D
+ * transforms of side2d x side2d (side2d a supported 3D axis length), packed
+ * back to back in one buffer in that order (fb_batch_offsets gives each
+ * start).  Forward transforms are unscaled; inverse ones divide by the
+ * transform size.  Lengths up to 4096 take one pencil pass; longer 1D
+ * lengths n = n1 n2 take two (a length-n1 pass over stride n2 into blocks of
+ * n1, then a pre-twiddled length-n2 pass over stride n1); 2D transforms take
+ * a row pass and a column pass.  The batch plan groups equal lengths so that
+ * each (length, pass) group is one launch, or a persistent kernel runs the
+ * tiles of all groups: one launch for the first phase (first passes, 2D
+ * rows, single-pass lengths) and one for the second (second passes, 2D
+ * columns), ordered on the stream. */
+typedef struct fb_batch fb_batch;
+
+/* NULL on error.  dtype must be FB_C64.  Synchronous (builds tables). */
+fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, int dtype);
+void fb_batch_destroy(fb_batch *b);                    /* NULL-safe */
+int64_t fb_batch_elements(const fb_batch *b);          /* complex elements of the packed buffer */
+/* Writes the n1d + n2d start offsets (in complex elements); returns the count. */
+int fb_batch_offsets(const fb_batch *b, int64_t *off);
+/* Workspace bytes fb_batch_exec needs: 0 out of place; a buffer as large as
+ * the packed data when in_place != 0 (in == out). */
+size_t fb_batch_workspace_bytes(const fb_batch *b, int in_place);
+int fb_batch_launches(const fb_batch *b);              /* launches of the per-group mode */
+const char *fb_batch_describe(const fb_batch *b);
+
+/* Executes the batch: in and out are device buffers of fb_batch_elements
+ * complex64 values (equal, or not overlapping).  workspace (256-byte
+ * aligned, at least fb_batch_workspace_bytes(b, in == out) bytes) is needed
+ * only in place; it may be NULL otherwise.  persistent = 1 uses the
+ * persistent kernel (two launches), 0 one launch per group. */
+fb_status fb_batch_exec(const fb_batch *b, const void *in, void *out, void *workspace, size_t workspace_bytes,
+                        int dir, int persistent, void *hip_stream);
+
+/* ---- Serving form ------------------------------------------------------
+ * A request loop with continuous batching: submitted spectral-block
+ * requests wait in a FIFO; a worker thread admits the head as soon as a
+ * stream slot is free and the request's device bytes (two grids and its
+ * checksums) fit in the HBM budget, so work of requests that arrive while
+ * others run overlaps on the device.  Plans (per shape and dtype) and device
+ * buffers (per size) stay resident; pooled buffers count against the budget.
+ * A request: its input grid is generated on the device from the stream seed
+ * SplitMix64(seed, request_key) (as fb_fill_uniform), transformed forward,
+ * then for t = 1..steps evolved (alpha, t), transformed back and
+ * checksummed; the checksums (and the final grid when want_grid) come back
+ * to host memory.  A result does not depend on what else runs. */
+#define FB_SERVE_MAX_STEPS 64
+
+typedef struct {
+    int64_t nx, ny, nz;
+    int dtype;              /* FB_C128 or FB_C64 */
+    int steps;              /* 1 .. FB_SERVE_MAX_STEPS */
+    double alpha;
+    uint64_t seed;
+    int64_t request_key;    /* selects the input stream */
+    int want_grid;          /* copy the final grid back */
+} fb_request;
+
+typedef struct {
+    int64_t id;             /* as returned by fb_server_submit */
+    int status;             /* FB_OK or a negative fb_status */
+    int64_t nx, ny, nz;
+    int dtype, steps;
+    double t_arrival, t_admit, t_done;   /* host steady-clock seconds */
+    int64_t grid_bytes;     /* size of the final grid (0 unless want_grid) */
+} fb_result;
+
+typedef struct {
+    size_t budget, bytes_allocated, peak_allocated;
+    int plans_cached, max_concurrent;
+    int64_t queued;
+} fb_server_info;
+
+typedef struct fb_server fb_server;
+
+/* budget_bytes >= 1 MiB, 1 <= n_streams <= 64; NULL on error.  Uses the
+ * device current at creation. */
+fb_server *fb_server_create(size_t budget_bytes, int n_streams);
+/* Queues a request; returns its id (>= 0) or a negative fb_status
+ * (FB_ERR_BUDGET if it could never fit the budget). */
+int64_t fb_server_submit(fb_server *s, const fb_request *r);
+/* Takes one finished request, if any: returns 1 and fills *out, copies up to
+ * sums_cap doubles of checksums (re, im per step) and, when grid_cap is
+ * large enough, the final grid; returns 0 when none is finished. */
+int fb_server_poll(fb_server *s, fb_result *out, double *sums, int sums_cap, void *grid, size_t grid_cap);
+/* Requests submitted and not yet taken by fb_server_poll's producer side. */
+int64_t fb_server_in_flight(fb_server *s);
+int fb_server_stats(fb_server *s, fb_server_info *info);
+/* Finishes queued and running requests, then releases everything. */
+void fb_server_destroy(fb_server *s);
+
 /* Per-launch timing of the library's kernels, for benchmarks.  While
  * enabled, every kernel the library enqueues is bracketed by two HIP events
  * on the stream it is launched on.  Process wide: not for concurrent use from

@@ -383,7 +383,7 @@ fb_plan *fb_fft3d_plan(int64_t nx, int64_t ny, int64_t nz, int dtype)
         d.total = A.rp.twlen;
         e = fb::launch_twiddles(d, p->tw64 + A.tw_off, p->tw32 + A.tw_off, nullptr);
     }
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
         hip_fail(e, "twiddle generation");
         fb_fft3d_destroy(p);
@@ -548,6 +548,426 @@ fb_status fb_fill_uniform(const fb_plan *p, void *x, uint64_t seed, void *hip_st
     if (check_device(p)) return (fb_status)g_code;
     hipError_t e = fb::launch_fill_uniform(p->esize, x, p->N, seed, (hipStream_t)hip_stream);
     if (e != hipSuccess) return (fb_status)hip_fail(e, "fill launch");
+    return (fb_status)ok();
+}
+
+}  // extern "C"
+
+// ======================================================================
+// Batched form: many independent complex64 1D transforms of mixed lengths
+// plus 2D transforms, packed back to back in one buffer.
+// ======================================================================
+
+#include <algorithm>
+#include <map>
+
+#include "fb_batch.hpp"
+
+struct fb_batch {
+    int n1d, n2d;
+    int64_t side2d;
+    int64_t total;                 // complex elements of the packed layout
+    std::vector<int64_t> len, off; // per transform (1D first, then 2D)
+    std::vector<fb::BatchGroup> groups;
+    int phase1_begin;                // first group of phase 1
+    int64_t ntasks[2];               // tiles per phase
+    fb::BatchGroup *groups_dev;
+    std::vector<void *> dev_allocs;  // tables, segment offsets
+    int device;
+    int nblocks;                     // persistent grid
+    std::string desc;
+};
+
+namespace {
+
+// Split of a long transform n = n1 * n2 into two strided passes (n1 first);
+// n2 is the power of two nearest sqrt(n) from above, at most 512.
+void batch_split(int64_t n, int64_t &n1, int64_t &n2)
+{
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= n) lg++;
+    int64_t k = (lg + 1) / 2 + ((lg + 1) % 2);   // ceil(log2(n) / 2), approximately
+    if (k > 9) k = 9;
+    n2 = int64_t(1) << k;
+    while (n2 > 2 && (n % n2 != 0 || n / n2 > 4096)) n2 >>= 1;
+    n1 = n / n2;
+}
+
+bool batch_length_ok(int64_t n)
+{
+    if (fb::supported_length(n)) return n >= 2;
+    if (n <= 4096 || n > 4096 * 512) return false;
+    int64_t n1, n2;
+    batch_split(n, n1, n2);
+    return n1 * n2 == n && fb::supported_length(n1) && fb::supported_length(n2) && n1 >= 2 && n2 >= 2;
+}
+
+template <class T> T *dev_alloc(fb_batch *b, size_t count, hipError_t &e)
+{
+    T *p = nullptr;
+    e = hipMalloc((void **)&p, count * sizeof(T) + 16);
+    if (e == hipSuccess) b->dev_allocs.push_back(p);
+    return p;
+}
+
+void batch_free(fb_batch *b)
+{
+    for (void *p : b->dev_allocs) (void)hipFree(p);
+    b->dev_allocs.clear();
+}
+
+// Fills the geometry of a pass over segments of `segp` pencils each.
+void set_geom(PassArgs &a, int64_t npencils, int64_t segp, const int64_t *seg_off, int64_t inner, int64_t outer,
+              int64_t istep, int64_t stride)
+{
+    a.npencils = npencils;
+    a.seg_pencils = segp;
+    a.seg_off = seg_off;
+    a.inner = inner;
+    a.outer = outer;
+    a.istep = istep;
+    a.stride = stride;
+}
+
+// Largest element touched by a group, relative to its segment start.
+bool group_in_bounds(const fb::BatchGroup &g, int64_t seg_max_off, int64_t total)
+{
+    const PassArgs &a = g.args;
+    const int64_t np = a.seg_pencils;
+    auto reach = [&](int64_t inner, int64_t outer, int64_t istep, int64_t stride) {
+        const int64_t in_max = (np < inner ? np : inner) - 1;
+        return ((np - 1) / inner) * outer + in_max * istep + (int64_t)(g.n - 1) * stride;
+    };
+    if (seg_max_off + reach(a.inner, a.outer, a.istep, a.stride) >= total) return false;
+    if (a.ostride && seg_max_off + reach(a.oinner, a.oouter, a.oistep, a.ostride) >= total) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, int dtype)
+{
+    if (dtype != FB_C64) {
+        fail(FB_ERR_DTYPE, "batched transforms support complex64 (FB_C64) only, got dtype %d", dtype);
+        return nullptr;
+    }
+    if (n1d < 0 || n2d < 0 || n1d + n2d < 1) {
+        fail(FB_ERR_INVALID_ARG, "need n1d >= 0, n2d >= 0 and at least one transform");
+        return nullptr;
+    }
+    if (n1d > 0 && !lens) {
+        fail(FB_ERR_INVALID_ARG, "lens is NULL");
+        return nullptr;
+    }
+    for (int i = 0; i < n1d; i++)
+        if (!batch_length_ok(lens[i])) {
+            fail(FB_ERR_UNSUPPORTED_SIZE, "1D length %lld (transform %d) is not supported (2^a or 3*2^a, 2..2^21)",
+                 (long long)lens[i], i);
+            return nullptr;
+        }
+    if (n2d > 0 && (side2d < 2 || !fb::supported_length(side2d))) {
+        fail(FB_ERR_UNSUPPORTED_SIZE, "2D side %lld is not supported", (long long)side2d);
+        return nullptr;
+    }
+    fb_batch *b = new (std::nothrow) fb_batch();
+    if (!b) {
+        fail(FB_ERR_OOM, "host allocation failed");
+        return nullptr;
+    }
+    b->n1d = n1d;
+    b->n2d = n2d;
+    b->side2d = side2d;
+    int64_t off = 0;
+    for (int i = 0; i < n1d; i++) {
+        b->len.push_back(lens[i]);
+        b->off.push_back(off);
+        off += lens[i];
+    }
+    for (int j = 0; j < n2d; j++) {
+        b->len.push_back(side2d * side2d);
+        b->off.push_back(off);
+        off += side2d * side2d;
+    }
+    b->total = off;
+
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) {
+        hip_fail(e, "hipGetDevice");
+        delete b;
+        return nullptr;
+    }
+
+    // transforms by length
+    std::map<int64_t, std::vector<int64_t>> by_len;
+    for (int i = 0; i < n1d; i++) by_len[lens[i]].push_back(b->off[i]);
+
+    // stage twiddle tables per pass length, pre-twiddles per long length
+    std::map<int64_t, float2 *> stage_tw;
+    std::map<int64_t, float2 *> roots;
+    double2 *scratch64 = nullptr;
+    auto stage_table = [&](int64_t n) -> float2 * {
+        auto it = stage_tw.find(n);
+        if (it != stage_tw.end()) return it->second;
+        fb::RadixPlan rp = fb::radix_plan((int)n);
+        const int cnt = rp.twlen > 0 ? rp.twlen : 1;
+        float2 *t32 = dev_alloc<float2>(b, cnt, e);
+        if (e != hipSuccess) return nullptr;
+        if (rp.twlen > 0) {
+            double2 *t64 = dev_alloc<double2>(b, cnt, e);
+            if (e != hipSuccess) return nullptr;
+            fb::TwDesc d{};
+            d.nst = rp.count;
+            for (int s = 0; s < rp.count; s++) {
+                d.r[s] = rp.r[s];
+                d.ns[s] = rp.ns[s];
+                d.off[s] = rp.twoff[s];
+            }
+            d.total = rp.twlen;
+            e = fb::launch_twiddles(d, t64, t32, nullptr);
+        }
+        stage_tw[n] = t32;
+        return t32;
+    };
+    (void)scratch64;
+
+    std::vector<fb::BatchGroup> pass1, single, pass2;
+    auto new_group = [&](int64_t n, bool contig) {
+        fb::BatchGroup g{};
+        g.n = (int)n;
+        g.contig = contig ? 1 : 0;
+        g.phase = 0;
+        g.args.tw = stage_table(n);
+        g.inv_scale = 1.0;
+        return g;
+    };
+    const int esize = 8;
+    for (auto &kv : by_len) {
+        const int64_t L = kv.first;
+        const int64_t cnt = (int64_t)kv.second.size();
+        int64_t *soff = dev_alloc<int64_t>(b, kv.second.size(), e);
+        if (e == hipSuccess)
+            e = hipMemcpy(soff, kv.second.data(), kv.second.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) break;
+        const int64_t segmax = kv.second.back();
+        if (L <= 4096) {
+            fb::BatchGroup g = new_group(L, true);
+            set_geom(g.args, cnt, 1, soff, 1, L, 0, 1);
+            g.in_sel = 0;
+            g.out_sel = 1;
+            g.last = 1;
+            g.inv_scale = 1.0 / (double)L;
+            g.ntiles = (cnt + fb::find_pass(esize, (int)L, true, false).pencils_per_wg - 1) /
+                       fb::find_pass(esize, (int)L, true, false).pencils_per_wg;
+            if (!group_in_bounds(g, segmax, b->total)) e = hipErrorInvalidValue;
+            single.push_back(g);
+        } else {
+            int64_t n1, n2;
+            batch_split(L, n1, n2);
+            // pass 1: length-n1 DFTs over b < n2 (elements b + q n2), output to b n1 + q
+            fb::BatchGroup g1 = new_group(n1, false);
+            set_geom(g1.args, cnt * n2, n2, soff, n2, 0, 1, n2);
+            g1.args.oinner = 1;
+            g1.args.oouter = n1;
+            g1.args.oistep = 0;
+            g1.args.ostride = 1;
+            g1.in_sel = 0;
+            g1.out_sel = 2;   // fixed up per execution when out != in
+            g1.last = 0;
+            const int P1 = fb::find_pass(esize, (int)n1, false, false).pencils_per_wg;
+            g1.ntiles = (cnt * n2 + P1 - 1) / P1;
+            // pass 2: pre-twiddle w_L^(q b), length-n2 DFTs over b < n1 (elements b + q n1)
+            fb::BatchGroup g2 = new_group(n2, false);
+            set_geom(g2.args, cnt * n1, n1, soff, n1, 0, 1, n1);
+            auto it = roots.find(L);
+            float2 *rt = nullptr;
+            if (it != roots.end()) rt = it->second;
+            else {
+                rt = dev_alloc<float2>(b, L, e);
+                if (e == hipSuccess) e = fb::launch_roots(L, nullptr, rt, nullptr);
+                roots[L] = rt;
+            }
+            g2.args.ptw = rt;
+            g2.args.ptw_len = L;
+            g2.in_sel = 2;
+            g2.out_sel = 1;
+            g2.last = 1;
+            g2.inv_scale = 1.0 / (double)L;
+            const int P2 = fb::find_pass(esize, (int)n2, false, false).pencils_per_wg;
+            g2.ntiles = (cnt * n1 + P2 - 1) / P2;
+            if (!group_in_bounds(g1, segmax, b->total) || !group_in_bounds(g2, segmax, b->total))
+                e = hipErrorInvalidValue;
+            g2.phase = 1;
+            pass1.push_back(g1);
+            pass2.push_back(g2);
+        }
+        if (e != hipSuccess) break;
+    }
+    fb::BatchGroup rows{}, cols{};
+    bool has2d = n2d > 0 && e == hipSuccess;
+    if (has2d) {
+        std::vector<int64_t> o2(b->off.begin() + n1d, b->off.end());
+        int64_t *soff = dev_alloc<int64_t>(b, o2.size(), e);
+        if (e == hipSuccess) e = hipMemcpy(soff, o2.data(), o2.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+        const int64_t s = side2d;
+        rows = new_group(s, true);
+        set_geom(rows.args, n2d * s, s, soff, 1, s, 0, 1);
+        rows.in_sel = 0;
+        rows.out_sel = 1;
+        rows.ntiles = (n2d * s + fb::find_pass(esize, (int)s, true, false).pencils_per_wg - 1) /
+                      fb::find_pass(esize, (int)s, true, false).pencils_per_wg;
+        cols = new_group(s, false);
+        set_geom(cols.args, n2d * s, s, soff, s, 0, 1, s);
+        cols.in_sel = 1;
+        cols.out_sel = 1;
+        cols.last = 1;
+        cols.phase = 1;
+        cols.inv_scale = 1.0 / (double)(s * s);
+        cols.ntiles = (n2d * s + fb::find_pass(esize, (int)s, false, false).pencils_per_wg - 1) /
+                      fb::find_pass(esize, (int)s, false, false).pencils_per_wg;
+        if (e == hipSuccess && (!group_in_bounds(rows, o2.back(), b->total) || !group_in_bounds(cols, o2.back(), b->total)))
+            e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) {
+        if (e == hipErrorInvalidValue) fail(FB_ERR_INVALID_ARG, "internal: batch geometry out of bounds");
+        else hip_fail(e, "batch plan");
+        batch_free(b);
+        delete b;
+        return nullptr;
+    }
+    // phase 0: first passes, 2D rows, single-pass transforms; phase 1: second
+    // passes and 2D columns (they read what phase 0 wrote)
+    for (auto &g : pass1) b->groups.push_back(g);
+    if (has2d) b->groups.push_back(rows);
+    for (auto &g : single) b->groups.push_back(g);
+    b->phase1_begin = (int)b->groups.size();
+    for (auto &g : pass2) b->groups.push_back(g);
+    if (has2d) b->groups.push_back(cols);
+    if ((int)b->groups.size() > FB_BATCH_MAX_GROUPS) {
+        fail(FB_ERR_UNSUPPORTED_SIZE, "too many distinct lengths in one batch (%d groups, at most %d)",
+             (int)b->groups.size(), FB_BATCH_MAX_GROUPS);
+        batch_free(b);
+        delete b;
+        return nullptr;
+    }
+    int64_t task[2] = {0, 0};
+    for (auto &g : b->groups) {
+        g.task0 = task[g.phase];
+        task[g.phase] += g.ntiles;
+    }
+    b->ntasks[0] = task[0];
+    b->ntasks[1] = task[1];
+    b->groups_dev = dev_alloc<fb::BatchGroup>(b, b->groups.size(), e);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->groups_dev, b->groups.data(), b->groups.size() * sizeof(fb::BatchGroup), hipMemcpyHostToDevice);
+    int per_cu = 0, cus = 0;
+    if (e == hipSuccess) e = fb::batch_occupancy(&per_cu);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        hip_fail(e, "batch plan");
+        batch_free(b);
+        delete b;
+        return nullptr;
+    }
+    b->nblocks = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    char d[256];
+    snprintf(d, sizeof d, "batch n1d=%d n2d=%d side=%lld groups=%d tiles=%lld+%lld elements=%lld", n1d, n2d,
+             (long long)side2d, (int)b->groups.size(), (long long)b->ntasks[0], (long long)b->ntasks[1],
+             (long long)b->total);
+    b->desc = d;
+    ok();
+    return b;
+}
+
+void fb_batch_destroy(fb_batch *b)
+{
+    if (!b) return;
+    batch_free(b);
+    delete b;
+}
+
+int64_t fb_batch_elements(const fb_batch *b) { return b ? b->total : 0; }
+
+int fb_batch_offsets(const fb_batch *b, int64_t *off)
+{
+    if (!b || !off) return fail(FB_ERR_INVALID_ARG, "NULL argument");
+    for (size_t i = 0; i < b->off.size(); i++) off[i] = b->off[i];
+    ok();
+    return (int)b->off.size();
+}
+
+size_t fb_batch_workspace_bytes(const fb_batch *b, int in_place)
+{
+    if (!b) return 0;
+    return in_place ? (size_t)b->total * 8 : 0;
+}
+
+int fb_batch_launches(const fb_batch *b) { return b ? (int)b->groups.size() : 0; }
+
+const char *fb_batch_describe(const fb_batch *b) { return b ? b->desc.c_str() : ""; }
+
+fb_status fb_batch_exec(const fb_batch *b, const void *in, void *out, void *workspace, size_t workspace_bytes, int dir,
+                        int persistent, void *hip_stream)
+{
+    if (!b) return (fb_status)fail(FB_ERR_INVALID_ARG, "batch plan is NULL");
+    if (!in || !out || (uintptr_t)in % 8 || (uintptr_t)out % 8)
+        return (fb_status)fail(FB_ERR_INVALID_ARG, "in/out must be non-NULL and 8-byte aligned");
+    if (dir != FB_FORWARD && dir != FB_INVERSE)
+        return (fb_status)fail(FB_ERR_INVALID_ARG, "dir must be FB_FORWARD (-1) or FB_INVERSE (+1), got %d", dir);
+    const size_t bytes = (size_t)b->total * 8;
+    const uintptr_t x = (uintptr_t)in, y = (uintptr_t)out;
+    const bool in_place = x == y;
+    if (!in_place && x < y + bytes && y < x + bytes)
+        return (fb_status)fail(FB_ERR_INVALID_ARG, "fb_batch_exec: buffers partially overlap");
+    const size_t need = fb_batch_workspace_bytes(b, in_place ? 1 : 0);
+    if (need && (!workspace || workspace_bytes < need || (uintptr_t)workspace % 256))
+        return (fb_status)fail(FB_ERR_INVALID_ARG, "in-place execution needs a 256-byte aligned workspace of %zu bytes",
+                               need);
+    void *wsdata = workspace;
+    if (in_place) {
+        const uintptr_t w = (uintptr_t)wsdata;
+        if (w < x + bytes && x < w + bytes) return (fb_status)fail(FB_ERR_INVALID_ARG, "workspace overlaps the data");
+    }
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return (fb_status)hip_fail(e, "hipGetDevice");
+    if (cur != b->device) return (fb_status)fail(FB_ERR_INVALID_ARG, "batch plan belongs to device %d", b->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    // first passes of long transforms write into the output when it is a
+    // separate buffer, else into the workspace
+    void *mid = in_place ? wsdata : out;
+    fb::BatchBuffers bufs{};
+    bufs.p[0] = (void *)in;
+    bufs.p[1] = out;
+    bufs.p[2] = mid;
+    bufs.inv = dir > 0;
+    if (persistent) {
+        const int ng = (int)b->groups.size();
+        e = timed_launch("batch_persistent<c64,phase0>", 0.0, st, [&] {
+            return fb::launch_batch_persistent(b->groups_dev, 0, b->phase1_begin, b->ntasks[0], b->nblocks, bufs, st);
+        });
+        if (e == hipSuccess)
+            e = timed_launch("batch_persistent<c64,phase1>", 0.0, st, [&] {
+                return fb::launch_batch_persistent(b->groups_dev, b->phase1_begin, ng, b->ntasks[1], b->nblocks, bufs,
+                                                   st);
+            });
+        if (e != hipSuccess) return (fb_status)hip_fail(e, "persistent batch launch");
+        return (fb_status)ok();
+    }
+    for (const fb::BatchGroup &g : b->groups) {
+        PassArgs a = g.args;
+        a.in = bufs.p[g.in_sel];
+        a.out = bufs.p[g.out_sel];
+        a.inv = bufs.inv;
+        a.scale = (bufs.inv && g.last) ? g.inv_scale : 1.0;
+        const PassInfo pi = fb::find_pass(8, g.n, g.contig != 0, false);
+        char name[96];
+        snprintf(name, sizeof name, "fft_pass<c64,n=%d,%s>", g.n, g.contig ? "contiguous" : "strided");
+        e = timed_launch(name, 0.0, st, [&] { return pi.launch(a, st); });
+        if (e != hipSuccess) return (fb_status)hip_fail(e, "batch pass launch");
+    }
     return (fb_status)ok();
 }
 

@@ -1,0 +1,121 @@
+// fb_batch.hip -- device side of the batched form: many independent 1D and
+// 2D complex64 transforms of mixed lengths, executed either as one launch
+// per (length, pass) group or as a single persistent launch that takes the
+// tiles of every group from a work queue.
+//
+// A batch is a list of groups; every group is one pencil pass (PassArgs)
+// over all transforms of one length, with `ntiles` tiles.  Groups come in
+// two phases: phase 0 holds the first passes of two-pass long transforms,
+// the row passes of 2D transforms and the single-pass lengths; phase 1 the
+// second passes and the column passes, which read what phase 0 wrote.
+#include <hip/hip_runtime.h>
+
+#include "fb_batch.hpp"
+#include "fb_pass.hpp"
+
+namespace fb {
+
+// Tile kinds of the persistent kernel: every complex64 pass length, in the
+// contiguous and the strided geometry.
+#define FB_BATCH_KINDS(X) \
+    X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) \
+    X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096)
+
+constexpr int max_int(int a, int b) { return a > b ? a : b; }
+
+template <int N> constexpr int kind_threads()
+{
+    return max_int(PassCfg<float2, N, true>::THREADS, PassCfg<float2, N, false>::THREADS);
+}
+template <int N> constexpr int kind_lds()
+{
+    return max_int(PassCfg<float2, N, true>::P * PassCfg<float2, N, true>::LS,
+                   PassCfg<float2, N, false>::P * PassCfg<float2, N, false>::LS);
+}
+
+constexpr int batch_threads()
+{
+    int m = 0;
+#define FB_MAXT(L) m = max_int(m, kind_threads<L>());
+    FB_BATCH_KINDS(FB_MAXT)
+#undef FB_MAXT
+    return m;
+}
+constexpr int batch_lds_elems()
+{
+    int m = 0;
+#define FB_MAXL(L) m = max_int(m, kind_lds<L>());
+    FB_BATCH_KINDS(FB_MAXL)
+#undef FB_MAXL
+    return m;
+}
+
+constexpr int BATCH_THREADS = batch_threads();
+constexpr int BATCH_LDS = batch_lds_elems();
+static_assert(BATCH_THREADS % 64 == 0 && BATCH_THREADS <= 1024, "persistent workgroup size");
+static_assert(BATCH_LDS * 8 <= 160 * 1024, "persistent kernel LDS");
+
+int batch_persistent_threads() { return BATCH_THREADS; }
+
+// Each tile kind is compiled as a function of its own, so that the register
+// allocation of one kind does not burden the others.  The group descriptor
+// is read through a wave-uniform pointer (scalar loads), so every branch in
+// the tile around a barrier is uniform.
+template <int L, bool CONTIG>
+__device__ __noinline__ void tile_fn(const BatchGroup *g, BatchBuffers bufs, int64_t tile, int tid, float2 *lds)
+{
+    PassArgs a = g->args;
+    a.in = bufs.p[g->in_sel];
+    a.out = bufs.p[g->out_sel];
+    a.inv = bufs.inv;
+    a.scale = (bufs.inv && g->last) ? g->inv_scale : 1.0;
+    pass_tile<float2, L, CONTIG, false>(a, tile, tid, lds, nullptr);
+}
+
+__device__ __forceinline__ void run_tile(const BatchGroup *g, const BatchBuffers &bufs, int64_t tile, int tid,
+                                         float2 *lds)
+{
+    switch (g->n * 2 + (g->contig ? 1 : 0)) {
+#define FB_KIND(L)                                                        \
+    case 2 * L + 1: tile_fn<L, true>(g, bufs, tile, tid, lds); break; \
+    case 2 * L: tile_fn<L, false>(g, bufs, tile, tid, lds); break;
+        FB_BATCH_KINDS(FB_KIND)
+#undef FB_KIND
+    default: break;
+    }
+}
+
+// Persistent execution of one phase: the tiles of groups [g0, g1) are
+// numbered 0 .. ntasks-1 in group order and workgroup w takes tiles
+// w, w + gridDim.x, w + 2 gridDim.x, ...  Groups of one phase are independent
+// of each other; a phase that depends on another is launched after it on the
+// same stream.  There is no communication between workgroups.
+__global__ void __launch_bounds__(BATCH_THREADS) batch_persistent(const BatchGroup *__restrict__ groups, int g0,
+                                                                  int g1, int64_t ntasks, BatchBuffers bufs)
+{
+    __shared__ float2 lds[BATCH_LDS];
+    const int tid = threadIdx.x;
+    int g = g0;
+    for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        while (g + 1 < g1 && t >= groups[g + 1].task0) g++;
+        run_tile(groups + g, bufs, t - groups[g].task0, tid, lds);
+        __syncthreads();   // the next tile reuses the LDS
+    }
+}
+
+hipError_t launch_batch_persistent(const BatchGroup *groups_dev, int g0, int g1, int64_t ntasks, int nblocks,
+                                   const BatchBuffers &bufs, hipStream_t st)
+{
+    if (ntasks <= 0) return hipSuccess;
+    const int64_t blocks = ntasks < nblocks ? ntasks : nblocks;
+    hipLaunchKernelGGL(batch_persistent, dim3((unsigned)blocks), dim3(BATCH_THREADS), 0, st, groups_dev, g0, g1,
+                       ntasks, bufs);
+    return hipGetLastError();
+}
+
+hipError_t batch_occupancy(int *blocks_per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent, BATCH_THREADS, 0);
+}
+
+}  // namespace fb

@@ -1,0 +1,41 @@
+// fb_batch.hpp -- shared between the batch plan (host) and fb_batch.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fb_internal.hpp"
+
+namespace fb {
+
+#define FB_BATCH_MAX_GROUPS 512
+
+// One (length, pass) group of a batch.  The data pointers of `args` are
+// chosen per execution: in_sel / out_sel name the buffer (0 = the caller's
+// input, 1 = the caller's output, 2 = the workspace data region).
+struct BatchGroup {
+    PassArgs args;
+    int n;          // pass length
+    int contig;     // 1: contiguous geometry, 0: strided
+    int phase;      // 0 or 1; phase 1 groups read what phase 0 wrote
+    int in_sel, out_sel;
+    int last;       // 1 when this pass completes its transforms (inverse scale applies)
+    double inv_scale;
+    int64_t ntiles;
+    int64_t task0;  // index of the group's first tile within its phase
+};
+
+// Buffers of one execution: p[0] input, p[1] output, p[2] intermediate.
+struct BatchBuffers {
+    void *p[3];
+    int inv;
+};
+
+int batch_persistent_threads();
+hipError_t batch_occupancy(int *blocks_per_cu);
+hipError_t launch_batch_persistent(const BatchGroup *groups_dev, int g0, int g1, int64_t ntasks, int nblocks,
+                                   const BatchBuffers &bufs, hipStream_t st);
+
+// tables[m] = w_n^m = exp(-2 pi i m / n), m < n, binary64 and binary32
+hipError_t launch_roots(int64_t n, double2 *t64, float2 *t32, hipStream_t st);
+
+}  // namespace fb

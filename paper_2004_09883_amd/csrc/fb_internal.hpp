@@ -14,7 +14,18 @@ struct PassArgs {
     void *out;
     const void *tw;     // per-stage twiddle table of this axis (same real type as the data)
     int64_t npencils;
-    int64_t inner, outer, istep, stride;
+    int64_t inner, outer, istep, stride;  // input geometry
+    // output geometry; when ostride == 0 the output uses the input geometry
+    int64_t oinner, oouter, oistep, ostride;
+    // segmented batches: when seg_off is set, pencil p belongs to segment
+    // p / seg_pencils, whose data starts at element seg_off[p / seg_pencils];
+    // the geometry above then applies to the local pencil p % seg_pencils
+    const int64_t *seg_off;
+    int64_t seg_pencils;
+    // pre-twiddle on load (two-pass long transforms): element q of local
+    // pencil b is multiplied by ptw[(q b) mod ptw_len], ptw[m] = w_L^m
+    const void *ptw;
+    int64_t ptw_len;
     int inv;            // 1: inverse (conjugate on load and on store)
     double scale;       // applied on store (1/N in the last inverse pass)
     // fused spectral evolution (contiguous passes only): element i of pencil

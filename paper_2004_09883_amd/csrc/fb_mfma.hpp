@@ -85,43 +85,49 @@ __device__ __forceinline__ f32x4 mx_dot(const bf16x8 *w, bf16x8 xh, bf16x8 xl)
     return acc;
 }
 
-// One radix-16 stage of a pass on the matrix cores, LDS to LDS.
+// One radix-16 stage of a pass on the matrix cores.
 //
-// The workgroup's pencil rows live in LDS (`lds`, row stride LS, padded
-// positions); the stage input q of butterfly b of pencil pp is
-// row[pp][b + q N/16].  Wave w takes the four groups 4w .. 4w+3 of 16
-// butterflies (butterfly beta = 16 group + lane%16, pencil beta / (N/16),
-// b = beta % (N/16)); the workgroup has exactly P N / 16 threads, so the
-// groups cover every butterfly once.  Inputs are read and twiddled first;
-// after a barrier the outputs are written to their Stockham positions
-// (b div Ns) Ns 16 + (b mod Ns) + k Ns; a second barrier ends the stage.
-template <int N, int LS, int Ns, int TWOFF>
-__device__ __forceinline__ void mx_stage16(float2 *lds, const float2 *__restrict__ tw, const MxConsts &A,
-                                           int wave, int lane)
+// Wave w takes the four groups 4w .. 4w+3 of 16 butterflies; lane (c, g)
+// of group gamma works on butterfly beta = 16 gamma + c, whose pencil and
+// index b come from `map` (beta -> pp, b), and supplies its inputs
+// q = 4g .. 4g+3 and receives its outputs k = 4g .. 4g+3.  The tile has
+// exactly P N / 16 threads, so the groups cover every butterfly once; waves
+// beyond the tile (`active` false, whole wavefronts) only take part in the
+// barriers.
+//
+// Inputs come from `src` (element b + q N/16 of the pencil, twiddled here by
+// w_{16 Ns}^(q (b mod Ns)) when Ns > 1) and outputs go to `dst` at the
+// Stockham positions (b div Ns) 16 Ns + (b mod Ns) + k Ns.  src and dst are
+// either the LDS rows of the tile or the grid in global memory; when both
+// are LDS a barrier separates the reads from the writes, and when dst is LDS
+// a barrier ends the stage.
+template <int N, int Ns, int TWOFF, bool SRC_LDS, bool DST_LDS, class Map, class Src, class Dst>
+__device__ __forceinline__ void mx_stage16(const float2 *__restrict__ tw, const MxConsts &A, int wave, int lane,
+                                           bool active, const Map &map, const Src &src, const Dst &dst)
 {
     constexpr int NBF = N / 16;
     const int c = lane & 15, g = lane >> 4;
     float2 x[4][4];
-    int rowoff[4], bb[4];
+    int ppv[4], bb[4];
 #pragma unroll
-    for (int gi = 0; gi < 4; gi++) {
+    for (int gi = 0; active && gi < 4; gi++) {
         const int beta = 16 * (4 * wave + gi) + c;
-        const int pp = beta / NBF, b = beta % NBF;
-        rowoff[gi] = pp * LS;
-        bb[gi] = b;
+        map(beta, ppv[gi], bb[gi]);
+        const int b = bb[gi];
+        const auto h = src.open(ppv[gi]);
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             const int q = 4 * g + i;
-            float2 v = lds[rowoff[gi] + lds_pos(b + q * NBF)];
+            float2 v = src.load(h, b + q * NBF);
             if constexpr (Ns > 1) {
                 if (q > 0) v = cmul(v, tw[TWOFF + (q - 1) * Ns + (b % Ns)]);
             }
             x[gi][i] = v;
         }
     }
-    __syncthreads();
+    if constexpr (SRC_LDS && DST_LDS) __syncthreads();
 #pragma unroll
-    for (int gi = 0; gi < 4; gi++) {
+    for (int gi = 0; active && gi < 4; gi++) {
         bf16x8 xh, xl;
 #pragma unroll
         for (int i = 0; i < 4; i++) {
@@ -135,13 +141,23 @@ __device__ __forceinline__ void mx_stage16(float2 *lds, const float2 *__restrict
         const f32x4 yi = mx_dot(A.ai, xh, xl);
         const int b = bb[gi];
         const int idx = (b / Ns) * Ns * 16 + (b % Ns);
+        const auto h = dst.open(ppv[gi]);
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             const int k = 4 * g + e;
-            lds[rowoff[gi] + lds_pos(idx + k * Ns)] = make_float2(yr[e], yi[e]);
+            dst.store(h, idx + k * Ns, make_float2(yr[e], yi[e]));
         }
     }
-    __syncthreads();
+    if constexpr (DST_LDS) __syncthreads();
 }
+
+// LDS rows of a tile as a source or destination of a matrix-core stage.
+struct MxLds {
+    float2 *lds;
+    int LS;
+    __device__ __forceinline__ float2 *open(int pp) const { return lds + pp * LS; }
+    __device__ __forceinline__ float2 load(float2 *row, int pos) const { return row[lds_pos(pos)]; }
+    __device__ __forceinline__ void store(float2 *row, int pos, float2 v) const { row[lds_pos(pos)] = v; }
+};
 
 }  // namespace fb

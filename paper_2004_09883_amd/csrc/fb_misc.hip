@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fb_device.hpp"
+#include "fb_batch.hpp"
 #include "fb_internal.hpp"
 
 namespace fb {
@@ -61,6 +62,24 @@ hipError_t launch_twiddles(const TwDesc &d, double2 *tw64, float2 *tw32, hipStre
     const int threads = 256;
     const int blocks = (d.total + threads - 1) / threads;
     hipLaunchKernelGGL(twiddle_kernel, dim3(blocks), dim3(threads), 0, st, d, tw64, tw32);
+    return hipGetLastError();
+}
+
+// w_n^m for every m < n (pre-twiddles of the two-pass long transforms)
+__global__ void roots_kernel(int64_t n, double2 *t64, float2 *t32)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const double2 w = root_of_unity(m, n);
+    if (t64) t64[m] = w;
+    t32[m] = make_float2((float)w.x, (float)w.y);
+}
+
+hipError_t launch_roots(int64_t n, double2 *t64, float2 *t32, hipStream_t st)
+{
+    const int threads = 256;
+    const int64_t blocks = (n + threads - 1) / threads;
+    hipLaunchKernelGGL(roots_kernel, dim3((unsigned)blocks), dim3(threads), 0, st, n, t64, t32);
     return hipGetLastError();
 }
 

@@ -16,14 +16,17 @@
 //
 // Pencil geometry: pencil p starts at element
 //     base(p) = (p / inner) * outer + (p % inner) * istep
-// and has element stride `stride`.  A contiguous pass (z axis) has
+// and has element stride `stride` (the output may use a geometry of its own,
+// and a batch of equal-length transforms may place each segment of pencils
+// at its own offset; see PassArgs).  A contiguous pass (z axis) has
 // stride 1 and pencils back to back; a strided pass (y or x axis) takes P
 // adjacent pencils per workgroup so that each row access covers P
 // consecutive elements.
 //
 // MX (complex64 only): the radix-16 stages run on the matrix cores
-// (fb_mfma.hpp), LDS to LDS; the other stages, the twiddles and the global
-// loads and stores stay on the vector units.
+// (fb_mfma.hpp); the first and last of them read and write global memory
+// themselves where the tile allows it (see MxStage::direct), the others work
+// LDS to LDS.  The remaining stages and the twiddles stay on the vector units.
 #pragma once
 #include "fb_device.hpp"
 #include "fb_internal.hpp"
@@ -54,13 +57,148 @@ template <typename V, int N, bool CONTIG> constexpr bool mx_capable()
     return sizeof(V) == 8 && has16 && N % 16 == 0 && Cfg::THREADS % 64 == 0;
 }
 
+// Streaming global access: the grid is read once and written once per pass,
+// so loads and stores can be marked non-temporal (FB_NT = 1).
+#ifndef FB_NT
+#define FB_NT 0
+#endif
+template <typename V> __device__ __forceinline__ V ld_stream(const V *p)
+{
+    if constexpr (FB_NT) {
+        typedef real_t<V> Rv __attribute__((ext_vector_type(2)));
+        const Rv r = __builtin_nontemporal_load((const Rv *)p);
+        return mk<V>(r.x, r.y);
+    } else {
+        return *p;
+    }
+}
+template <typename V> __device__ __forceinline__ void st_stream(V *p, V v)
+{
+    if constexpr (FB_NT) {
+        typedef real_t<V> Rv __attribute__((ext_vector_type(2)));
+        Rv r;
+        r.x = v.x;
+        r.y = v.y;
+        __builtin_nontemporal_store(r, (Rv *)p);
+    } else {
+        *p = v;
+    }
+}
+
 template <typename V, int N, bool CONTIG, bool MX> struct MxStage {
     // whether stage s runs on the matrix cores
     static constexpr bool at(int s) { return MX && PassCfg<V, N, CONTIG>::RP.r[s] == 16; }
+    // whether the first / last matrix-core stage reads / writes global memory
+    // itself: contiguous passes always (16 consecutive butterflies of one
+    // pencil are 16 consecutive elements), strided passes when 16 adjacent
+    // pencils fit in the tile (they are 16 consecutive elements)
+    static constexpr bool direct() { return MX && (CONTIG || PassCfg<V, N, CONTIG>::P % 16 == 0); }
 };
 
+// Butterfly numbering of the matrix-core stages: beta -> (pencil, b).
+template <int NBF> struct MxMapContig {
+    __device__ __forceinline__ void operator()(int beta, int &pp, int &b) const
+    {
+        pp = beta / NBF;
+        b = beta % NBF;
+    }
+};
+template <int P> struct MxMapStrided {
+    __device__ __forceinline__ void operator()(int beta, int &pp, int &b) const
+    {
+        pp = beta % P;
+        b = beta / P;
+    }
+};
+
+// Global memory as the source of the first matrix-core stage (complex64):
+// element pos of pencil pp of the tile, with the fused evolution factor and
+// the conjugation of an inverse applied as it is loaded.
+struct MxGlobalIn {
+    const PassArgs *a;
+    int64_t tile;
+    int P;
+    const float *gtab;
+    struct H {
+        const float2 *p;
+        float g;
+        bool ok;
+    };
+    __device__ __forceinline__ H open(int pp) const
+    {
+        H h{nullptr, 1.f, false};
+        const int64_t pq = tile * P + pp;
+        if (pq >= a->npencils) return h;
+        int64_t s0 = 0, l = pq;
+        if (a->seg_off) {
+            s0 = a->seg_off[pq / a->seg_pencils];
+            l = pq % a->seg_pencils;
+        }
+        h.p = (const float2 *)a->in + s0 + (l / a->inner) * a->outer + (l % a->inner) * a->istep;
+        if (a->evolve) {
+            const int64_t pa = pq / a->ev_d, pb = pq % a->ev_d;
+            const double ka = (double)signed_k(pa, a->ev_la), kb = (double)signed_k(pb, a->ev_lb);
+            h.g = evol_factor<float>(a->ev_c, ka * ka + kb * kb);
+        }
+        h.ok = true;
+        return h;
+    }
+    __device__ __forceinline__ float2 load(const H &h, int pos) const
+    {
+        if (!h.ok) return make_float2(0.f, 0.f);
+        float2 v = ld_stream(h.p + (int64_t)pos * a->stride);
+        if (a->evolve) v = cscale(v, h.g * gtab[pos]);
+        if (a->inv) v = cconj(v);
+        return v;
+    }
+};
+
+// Global memory as the destination of the last matrix-core stage.
+struct MxGlobalOut {
+    const PassArgs *a;
+    int64_t tile;
+    int P;
+    struct H {
+        float2 *p;
+        bool ok;
+    };
+    __device__ __forceinline__ H open(int pp) const
+    {
+        H h{nullptr, false};
+        const int64_t pq = tile * P + pp;
+        if (pq >= a->npencils) return h;
+        int64_t s0 = 0, l = pq;
+        if (a->seg_off) {
+            s0 = a->seg_off[pq / a->seg_pencils];
+            l = pq % a->seg_pencils;
+        }
+        h.p = (float2 *)a->out + s0 +
+              (a->ostride ? (l / a->oinner) * a->oouter + (l % a->oinner) * a->oistep
+                          : (l / a->inner) * a->outer + (l % a->inner) * a->istep);
+        h.ok = true;
+        return h;
+    }
+    __device__ __forceinline__ void store(const H &h, int pos, float2 v) const
+    {
+        if (!h.ok) return;
+        if (a->inv) v = cconj(v);
+        if (a->scale != 1.0) v = cscale(v, (float)a->scale);
+        st_stream(h.p + (int64_t)pos * (a->ostride ? a->ostride : a->stride), v);
+    }
+};
+
+#ifdef FB_WAVES_PER_EU
+#define FB_OCCUPANCY __attribute__((amdgpu_waves_per_eu(FB_WAVES_PER_EU)))
+#else
+#define FB_OCCUPANCY
+#endif
+
+// One tile of a pass: P pencils of length N.  `lds` holds P * LS elements,
+// `gtab` N reals (contiguous passes).  The caller may run the tile on a
+// workgroup larger than the tile's THREADS (the persistent batch kernel):
+// the extra threads only take part in the barriers.
 template <typename V, int N, bool CONTIG, bool MX>
-__global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) fft_pass(PassArgs a)
+__device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int tid, V *lds, real_t<V> *gtab)
 {
     using Cfg = PassCfg<V, N, CONTIG>;
     using R = real_t<V>;
@@ -69,20 +207,25 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) fft_pass(Pas
     constexpr int NST = RP.count;
     static_assert(!MX || mx_capable<V, N, CONTIG>(), "no matrix-core variant for this pass");
 
-    __shared__ V lds[P * LS];
-    __shared__ R gtab[CONTIG ? N : 1];
-
-    const int tid = threadIdx.x;
+    const bool active = tid < Cfg::THREADS;
     const int t = CONTIG ? tid % T : tid / P;
     const int pp = CONTIG ? tid / T : tid % P;
-    const int64_t p = (int64_t)blockIdx.x * P + pp;
-    const bool valid = p < a.npencils;
-    const int64_t base = valid ? (p / a.inner) * a.outer + (p % a.inner) * a.istep : 0;
+    const int64_t p = tile * P + pp;
+    const bool valid = active && p < a.npencils;
+    int64_t seg0 = 0, lp = p;   // segment start and local pencil index
+    if (a.seg_off && valid) {
+        seg0 = a.seg_off[p / a.seg_pencils];
+        lp = p % a.seg_pencils;
+    }
+    const int64_t base = valid ? seg0 + (lp / a.inner) * a.outer + (lp % a.inner) * a.istep : 0;
+    const bool ogeom = a.ostride != 0;
+    const int64_t obase = !valid ? 0 : ogeom ? seg0 + (lp / a.oinner) * a.oouter + (lp % a.oinner) * a.oistep : base;
     const V *__restrict__ gin = (const V *)a.in + base;
-    V *__restrict__ gout = (V *)a.out + base;
+    V *__restrict__ gout = (V *)a.out + obase;
     const V *__restrict__ tw = (const V *)a.tw;
     const int64_t S = a.stride;
-    V *row = lds + pp * LS;
+    const int64_t OS = ogeom ? a.ostride : a.stride;
+    V *row = lds + (active ? pp : 0) * LS;
 
     V v[M];
 
@@ -90,7 +233,7 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) fft_pass(Pas
     R gab = (R)1;
     if constexpr (CONTIG) {
         if (a.evolve) {
-            for (int i = tid; i < N; i += Cfg::THREADS) {
+            for (int i = tid; active && i < N; i += Cfg::THREADS) {
                 const double k = (double)signed_k(i, N);
                 gtab[i] = evol_factor<R>(a.ev_c, k * k);
             }
@@ -103,18 +246,22 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) fft_pass(Pas
         }
     }
 
+    using MXS = MxStage<V, N, CONTIG, MX>;
+    constexpr bool MX_IN = MXS::at(0) && MXS::direct();         // first stage loads global itself
+    constexpr bool MX_OUT = MXS::at(NST - 1) && MXS::direct();  // last stage stores global itself
+
     // ---- stage 0 input: global loads, pattern b + q N/R0
     {
         constexpr int R0 = RP.r[0];
         constexpr int NBF = N / R0;
         constexpr int U = (NBF + T - 1) / T;
-        if (valid) {
+        if (valid && !MX_IN) {
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int b = t + T * u;
                 if (NBF % T == 0 || b < NBF) {
 #pragma unroll
-                    for (int q = 0; q < R0; q++) v[u * R0 + q] = gin[(int64_t)(b + q * NBF) * S];
+                    for (int q = 0; q < R0; q++) v[u * R0 + q] = ld_stream(gin + (int64_t)(b + q * NBF) * S);
                 }
             }
             if constexpr (CONTIG) {
@@ -133,11 +280,26 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) fft_pass(Pas
 #pragma unroll
                 for (int i = 0; i < M; i++) v[i] = cconj(v[i]);
             }
+            // pre-twiddle after the conjugation: an inverse is conj(DFT(conj(x))) as a whole
+            if (a.ptw) {
+                const V *__restrict__ ptw = (const V *)a.ptw;
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const int b = t + T * u;
+                    if (NBF % T == 0 || b < NBF) {
+#pragma unroll
+                        for (int q = 0; q < R0; q++) {
+                            const int64_t e = b + q * NBF;
+                            if (e > 0) v[u * R0 + q] = cmul(v[u * R0 + q], ptw[(e * lp) % a.ptw_len]);
+                        }
+                    }
+                }
+            }
         }
-        if constexpr (MxStage<V, N, CONTIG, MX>::at(0)) {
+        if constexpr (MXS::at(0) && !MX_IN) {
             // the matrix-core stage reads its inputs from LDS in natural order
 #pragma unroll
-            for (int u = 0; u < U; u++) {
+            for (int u = 0; active && u < U; u++) {
                 const int b = t + T * u;
                 if (NBF % T == 0 || b < NBF) {
 #pragma unroll
@@ -166,7 +328,7 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) fft_pass(Pas
                 constexpr int NBFp = N / Rp;
                 constexpr int Up = (NBFp + T - 1) / T;
 #pragma unroll
-                for (int u = 0; u < Up; u++) {
+                for (int u = 0; active && u < Up; u++) {
                     const int b = t + T * u;
                     if (NBFp % T == 0 || b < NBFp) {
                         const int idx = (b / Nsp) * Nsp * Rp + (b % Nsp);
@@ -176,8 +338,31 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) fft_pass(Pas
                 }
                 __syncthreads();
             }
-            if constexpr (std::is_same<V, float2>::value)
-                mx_stage16<N, LS, Ns, RP.twoff[s]>((float2 *)lds, (const float2 *)tw, mxc, tid >> 6, tid & 63);
+            if constexpr (std::is_same<V, float2>::value) {
+                constexpr bool IN_G = (s == 0) && MX_IN;
+                constexpr bool OUT_G = (s == NST - 1) && MX_OUT;
+                const MxLds ldsio{(float2 *)lds, LS};
+                const MxGlobalIn gin_io{&a, tile, P, (const float *)gtab};
+                const MxGlobalOut gout_io{&a, tile, P};
+                auto run = [&](const auto &map) {
+                    if constexpr (IN_G && OUT_G)
+                        mx_stage16<N, Ns, RP.twoff[s], false, false>((const float2 *)tw, mxc, tid >> 6, tid & 63,
+                                                                     active, map, gin_io, gout_io);
+                    else if constexpr (IN_G)
+                        mx_stage16<N, Ns, RP.twoff[s], false, true>((const float2 *)tw, mxc, tid >> 6, tid & 63,
+                                                                    active, map, gin_io, ldsio);
+                    else if constexpr (OUT_G)
+                        mx_stage16<N, Ns, RP.twoff[s], true, false>((const float2 *)tw, mxc, tid >> 6, tid & 63,
+                                                                    active, map, ldsio, gout_io);
+                    else
+                        mx_stage16<N, Ns, RP.twoff[s], true, true>((const float2 *)tw, mxc, tid >> 6, tid & 63,
+                                                                   active, map, ldsio, ldsio);
+                };
+                // strided tiles with direct access number butterflies pencil-fastest so that
+                // the 16 lanes of a group touch 16 adjacent pencils (consecutive addresses)
+                if constexpr (!CONTIG && MXS::direct()) run(MxMapStrided<P>{});
+                else run(MxMapContig<N / 16>{});
+            }
         } else {
             if constexpr (s > 0) {
                 if constexpr (!MxStage<V, N, CONTIG, MX>::at(s - 1)) {
@@ -187,7 +372,7 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) fft_pass(Pas
                     constexpr int NBFp = N / Rp;
                     constexpr int Up = (NBFp + T - 1) / T;
 #pragma unroll
-                    for (int u = 0; u < Up; u++) {
+                    for (int u = 0; active && u < Up; u++) {
                         const int b = t + T * u;
                         if (NBFp % T == 0 || b < NBFp) {
                             const int idx = (b / Nsp) * Nsp * Rp + (b % Nsp);
@@ -199,7 +384,7 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) fft_pass(Pas
                 }
                 // read this stage's inputs
 #pragma unroll
-                for (int u = 0; u < U; u++) {
+                for (int u = 0; active && u < U; u++) {
                     const int b = t + T * u;
                     if (NBF % T == 0 || b < NBF) {
 #pragma unroll
@@ -210,7 +395,7 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) fft_pass(Pas
             }
 
 #pragma unroll
-            for (int u = 0; u < U; u++) {
+            for (int u = 0; active && u < U; u++) {
                 const int b = t + T * u;
                 if (NBF % T == 0 || b < NBF) {
                     V *w = v + u * Rr;
@@ -230,10 +415,10 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) fft_pass(Pas
         constexpr int RL = RP.r[NST - 1];
         constexpr int NBF = N / RL;
         constexpr int U = (NBF + T - 1) / T;
-        if constexpr (MxStage<V, N, CONTIG, MX>::at(NST - 1)) {
+        if constexpr (MXS::at(NST - 1) && !MX_OUT) {
             // the matrix-core stage left the result in LDS in natural order
 #pragma unroll
-            for (int u = 0; u < U; u++) {
+            for (int u = 0; active && u < U; u++) {
                 const int b = t + T * u;
                 if (NBF % T == 0 || b < NBF) {
 #pragma unroll
@@ -241,7 +426,7 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) fft_pass(Pas
                 }
             }
         }
-        if (valid) {
+        if (valid && !MX_OUT) {
             const R sc = (R)a.scale;
 #pragma unroll
             for (int u = 0; u < U; u++) {
@@ -252,12 +437,21 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) fft_pass(Pas
                         V o = v[u * RL + q];
                         if (a.inv) o = cconj(o);
                         if (a.scale != 1.0) o = cscale(o, sc);
-                        gout[(int64_t)(b + q * NBF) * S] = o;
+                        st_stream(gout + (int64_t)(b + q * NBF) * OS, o);
                     }
                 }
             }
         }
     }
+}
+
+template <typename V, int N, bool CONTIG, bool MX>
+__global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) FB_OCCUPANCY fft_pass(PassArgs a)
+{
+    using Cfg = PassCfg<V, N, CONTIG>;
+    __shared__ V lds[Cfg::P * Cfg::LS];
+    __shared__ real_t<V> gtab[CONTIG ? N : 1];
+    pass_tile<V, N, CONTIG, MX>(a, blockIdx.x, threadIdx.x, lds, gtab);
 }
 
 }  // namespace fb

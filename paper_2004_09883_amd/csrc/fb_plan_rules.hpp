@@ -75,7 +75,24 @@ constexpr int lds_pencil_stride(int n)
     return (s % 2 == 0) ? s + 1 : s;
 }
 
-constexpr int lds_budget_bytes(bool contig) { return contig ? 40 * 1024 : 72 * 1024; }
+// Build-time tuning knobs (defaults are the measured best on MI355X).
+#ifndef FB_LDS_CONTIG_KB
+#define FB_LDS_CONTIG_KB 40
+#endif
+#ifndef FB_LDS_STRIDED_KB
+#define FB_LDS_STRIDED_KB 72
+#endif
+#ifndef FB_STRIDED_P16
+#define FB_STRIDED_P16 16   // target pencils per workgroup, strided complex128
+#endif
+#ifndef FB_STRIDED_P8
+#define FB_STRIDED_P8 32    // target pencils per workgroup, strided complex64
+#endif
+#ifndef FB_CONTIG_THREADS
+#define FB_CONTIG_THREADS 256
+#endif
+
+constexpr int lds_budget_bytes(bool contig) { return contig ? FB_LDS_CONTIG_KB * 1024 : FB_LDS_STRIDED_KB * 1024; }
 
 constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
 
@@ -92,7 +109,8 @@ constexpr bool pencils_fit(int P, int n, bool contig, int esize)
 constexpr int pencils_per_wg(int n, bool contig, int esize)
 {
     const int T = threads_per_pencil(n);
-    int P = contig ? (256 / T > 0 ? 256 / T : 1) : (esize == 16 ? 16 : 32);
+    int P = contig ? (FB_CONTIG_THREADS / T > 0 ? FB_CONTIG_THREADS / T : 1)
+                   : (esize == 16 ? FB_STRIDED_P16 : FB_STRIDED_P8);
     if (!contig && T == 1) P = 64;
     const int m = 64 / gcd_int(T, 64);
     if (P % m) {

@@ -32,7 +32,32 @@ DTYPE_NAMES = {FB_C128: "c128", FB_C64: "c64", FB_C64_SPLITBF16: "c64_splitbf16"
 EXPORTS = ("fb_version", "fb_last_error", "fb_describe_shape", "fb_fft3d_plan", "fb_fft3d_destroy",
            "fb_plan_device_bytes", "fb_plan_describe", "fb_fft3d_exec", "fb_spectral_evolve",
            "fb_checksum", "fb_spectral_step", "fb_fill_uniform", "fb_fft3d_exec_axes",
-           "fb_profile_enable", "fb_profile_report")
+           "fb_profile_enable", "fb_profile_report", "fb_batch_plan", "fb_batch_destroy", "fb_batch_elements",
+           "fb_batch_offsets", "fb_batch_workspace_bytes", "fb_batch_launches", "fb_batch_describe",
+           "fb_batch_exec", "fb_server_create", "fb_server_submit", "fb_server_poll",
+           "fb_server_in_flight", "fb_server_stats", "fb_server_destroy")
+
+
+FB_SERVE_MAX_STEPS = 64
+
+
+class FbRequest(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64), ("dtype", ctypes.c_int),
+                ("steps", ctypes.c_int), ("alpha", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("request_key", ctypes.c_int64), ("want_grid", ctypes.c_int)]
+
+
+class FbResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("nz", ctypes.c_int64), ("dtype", ctypes.c_int), ("steps", ctypes.c_int),
+                ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("grid_bytes", ctypes.c_int64)]
+
+
+class FbServerInfo(ctypes.Structure):
+    _fields_ = [("budget", ctypes.c_size_t), ("bytes_allocated", ctypes.c_size_t),
+                ("peak_allocated", ctypes.c_size_t), ("plans_cached", ctypes.c_int),
+                ("max_concurrent", ctypes.c_int), ("queued", ctypes.c_int64)]
 
 
 class FbError(RuntimeError):
@@ -71,6 +96,20 @@ def load():
         "fb_fft3d_exec_axes": (i32, [vp, vp, vp, i32, i32, vp]),
         "fb_profile_enable": (i32, [i32]),
         "fb_profile_report": (i32, [ctypes.c_char_p, i32]),
+        "fb_batch_plan": (vp, [ctypes.POINTER(i64), i32, i32, i64, i32]),
+        "fb_batch_destroy": (None, [vp]),
+        "fb_batch_elements": (i64, [vp]),
+        "fb_batch_offsets": (i32, [vp, ctypes.POINTER(i64)]),
+        "fb_batch_workspace_bytes": (ctypes.c_size_t, [vp, i32]),
+        "fb_batch_launches": (i32, [vp]),
+        "fb_batch_describe": (ctypes.c_char_p, [vp]),
+        "fb_batch_exec": (i32, [vp, vp, vp, vp, ctypes.c_size_t, i32, i32, vp]),
+        "fb_server_create": (vp, [ctypes.c_size_t, i32]),
+        "fb_server_submit": (i64, [vp, ctypes.POINTER(FbRequest)]),
+        "fb_server_poll": (i32, [vp, ctypes.POINTER(FbResult), ctypes.POINTER(dbl), i32, vp, ctypes.c_size_t]),
+        "fb_server_in_flight": (i64, [vp]),
+        "fb_server_stats": (i32, [vp, ctypes.POINTER(FbServerInfo)]),
+        "fb_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -226,3 +265,119 @@ def fb_spectral_step(plan: Plan, uhat0, x_out, alpha: float, t: float, out2=None
 def fb_fill_uniform(plan: Plan, x, seed: int, stream=None):
     plan.check_tensor(x, "x")
     _check(load().fb_fill_uniform(plan.handle, _ptr(x), int(seed) & 0xFFFFFFFFFFFFFFFF, _stream(stream)))
+
+
+class Batch:
+    """Owns an fb_batch*: n1d 1D transforms of the given lengths plus n2d 2D
+    side x side transforms, packed back to back (complex64)."""
+
+    def __init__(self, lens, n2d: int = 0, side2d: int = 0, dtype: int = FB_C64):
+        self._lib = load()
+        lens = [int(v) for v in lens]
+        arr = (ctypes.c_int64 * max(1, len(lens)))(*lens)
+        h = self._lib.fb_batch_plan(arr, len(lens), int(n2d), int(side2d), dtype)
+        if not h:
+            code, msg = fb_last_error()
+            raise FbError(code, msg)
+        self.handle = h
+        self.lens = lens
+        self.n2d = int(n2d)
+        self.side2d = int(side2d)
+        self.elements = int(self._lib.fb_batch_elements(h))
+        off = (ctypes.c_int64 * (len(lens) + self.n2d))()
+        _check(self._lib.fb_batch_offsets(h, off))
+        self.offsets = list(off)
+        self.launches = int(self._lib.fb_batch_launches(h))
+        self.description = self._lib.fb_batch_describe(h).decode()
+
+    def workspace_bytes(self, in_place: bool = False) -> int:
+        return int(self._lib.fb_batch_workspace_bytes(self.handle, 1 if in_place else 0))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.fb_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fb_batch_plan(lens, n2d: int = 0, side2d: int = 0, dtype: int = FB_C64) -> Batch:
+    return Batch(lens, n2d, side2d, dtype)
+
+
+def fb_batch_exec(batch: Batch, x_in, x_out, workspace, direction: int = FB_FORWARD, persistent: bool = True,
+                  stream=None):
+    """x_in/x_out: complex64 device tensors of batch.elements values; workspace:
+    a device tensor (uint8) of at least batch.workspace_bytes(x_in is x_out)."""
+    for t, name in ((x_in, "in"), (x_out, "out")):
+        if not isinstance(t, int) and (t.numel() != batch.elements or not t.is_contiguous()):
+            raise FbError(FB_ERR_INVALID_ARG, f"{name} must be a contiguous tensor of {batch.elements} elements")
+    wbytes = workspace.numel() * workspace.element_size() if not isinstance(workspace, int) else 1 << 62
+    _check(load().fb_batch_exec(batch.handle, _ptr(x_in), _ptr(x_out), _ptr(workspace), wbytes, direction,
+                                1 if persistent else 0, _stream(stream)))
+
+
+
+
+class Server:
+    """Owns an fb_server*: the continuous-batching request loop."""
+
+    def __init__(self, budget_bytes: int, n_streams: int = 8):
+        self._lib = load()
+        h = self._lib.fb_server_create(int(budget_bytes), int(n_streams))
+        if not h:
+            raise FbError(FB_ERR_INVALID_ARG, "fb_server_create failed (budget >= 1 MiB, 1..64 streams, a device)")
+        self.handle = h
+
+    def submit(self, nx, ny, nz, dtype, steps, alpha, seed, request_key, want_grid=False) -> int:
+        r = FbRequest(nx, ny, nz, dtype, steps, alpha, seed & 0xFFFFFFFFFFFFFFFF, request_key, 1 if want_grid else 0)
+        rid = self._lib.fb_server_submit(self.handle, ctypes.byref(r))
+        if rid < 0:
+            raise FbError(int(rid), "fb_server_submit rejected the request")
+        return int(rid)
+
+    def poll(self, grid_capacity: int = 0):
+        """One finished request as a dict, or None."""
+        res = FbResult()
+        sums = (ctypes.c_double * (2 * FB_SERVE_MAX_STEPS))()
+        grid = None
+        if grid_capacity:
+            if getattr(self, "_grid", None) is None or len(self._grid) < grid_capacity:
+                self._grid = ctypes.create_string_buffer(grid_capacity)
+            grid = self._grid
+            grid_capacity = len(grid)
+        got = self._lib.fb_server_poll(self.handle, ctypes.byref(res), sums, 2 * FB_SERVE_MAX_STEPS, grid,
+                                       grid_capacity)
+        if got <= 0:
+            return None
+        out = {k: getattr(res, k) for k, _ in FbResult._fields_}
+        out["checksums"] = [complex(sums[2 * i], sums[2 * i + 1]) for i in range(res.steps)]
+        out["grid"] = grid.raw[:res.grid_bytes] if (grid is not None and res.grid_bytes) else None
+        return out
+
+    def in_flight(self) -> int:
+        return int(self._lib.fb_server_in_flight(self.handle))
+
+    def stats(self) -> dict:
+        info = FbServerInfo()
+        _check(self._lib.fb_server_stats(self.handle, ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in FbServerInfo._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.fb_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fb_server_create(budget_bytes: int, n_streams: int = 8) -> Server:
+    return Server(budget_bytes, n_streams)

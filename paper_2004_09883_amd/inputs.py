@@ -110,3 +110,31 @@ def batch_lengths(count: int, seed: int) -> np.ndarray:
 def round_c64(x: np.ndarray) -> np.ndarray:
     """Round a complex128 grid to complex64 (round to nearest even, per part)."""
     return x.astype(np.complex64)
+
+
+SERVING_SHAPES = ((32, 32, 32), (64, 64, 64), (128, 128, 128), (256, 256, 256), (128, 256, 512))
+
+
+def unit_interval(seed: int, counters) -> np.ndarray:
+    """(h >> 11) * 2**-53 in [0, 1) from SplitMix64."""
+    h = splitmix64(seed, counters)
+    return (h >> np.uint64(11)).astype(np.float64) * 2.0**-53
+
+
+def serving_workload(count: int, rate: float, seed: int = 5):
+    """Poisson request stream: for request j the counters 4j .. 4j+3 of stream
+    ``seed`` give the exponential gap -ln(1 - u) / rate, the shape (uniform
+    over SERVING_SHAPES), the dtype (complex64 with probability 0.7, else
+    complex128) and the number of evolve steps (uniform in 1..10).
+
+    Returns a dict of arrays: arrival (seconds from the start), shape index,
+    is_c64, steps."""
+    j = np.arange(count, dtype=np.uint64)
+    u = [unit_interval(seed, 4 * j + np.uint64(k)) for k in range(4)]
+    gaps = -np.log1p(-u[0]) / rate
+    return {
+        "arrival": np.cumsum(gaps),
+        "shape": np.minimum((u[1] * len(SERVING_SHAPES)).astype(np.int64), len(SERVING_SHAPES) - 1),
+        "is_c64": u[2] < 0.7,
+        "steps": 1 + np.minimum((u[3] * 10).astype(np.int64), 9),
+    }

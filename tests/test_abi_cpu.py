@@ -85,3 +85,23 @@ def test_null_plan_calls_are_rejected():
 def test_last_error_clears_on_success():
     fb.fb_describe_shape(8, 8, 8)
     assert fb.fb_last_error() == (0, "")
+
+
+def test_batch_plan_rejects_before_device():
+    lib = fb.load()
+    import ctypes
+    arr = (ctypes.c_int64 * 3)(256, 5, 1024)
+    assert not lib.fb_batch_plan(arr, 3, 0, 0, fb.FB_C64)
+    assert fb.fb_last_error()[0] == fb.FB_ERR_UNSUPPORTED_SIZE
+    arr = (ctypes.c_int64 * 1)(1 << 22)
+    assert not lib.fb_batch_plan(arr, 1, 0, 0, fb.FB_C64)
+    assert fb.fb_last_error()[0] == fb.FB_ERR_UNSUPPORTED_SIZE
+    assert not lib.fb_batch_plan(arr, 0, 0, 0, fb.FB_C64)
+    assert fb.fb_last_error()[0] == fb.FB_ERR_INVALID_ARG
+    assert not lib.fb_batch_plan(arr, 0, 2, 500, fb.FB_C64)
+    assert fb.fb_last_error()[0] == fb.FB_ERR_UNSUPPORTED_SIZE
+    assert not lib.fb_batch_plan(arr, 0, 2, 512, fb.FB_C128)
+    assert fb.fb_last_error()[0] == fb.FB_ERR_DTYPE
+    assert lib.fb_batch_exec(None, 16, 16, 256, 1 << 20, -1, 1, None) == fb.FB_ERR_INVALID_ARG
+    assert lib.fb_batch_elements(None) == 0
+    lib.fb_batch_destroy(None)

@@ -312,3 +312,37 @@ def test_profile_hook_records_every_launch():
     assert "checksum<c128>" in names
     assert sum(r["launches"] for r in rep) == 3 + 3 + 1
     assert all(r["avg_ms"] > 0 for r in rep)
+
+
+def test_graph_replays_match_eager():
+    """The spectral block captured in a HIP graph: several replays, with eager
+    work and synchronisations between them, each equal to the eager result."""
+    shape, steps = (64, 32, 48), 4
+    plan = fb.Plan(*shape, fb.FB_C128)
+    x0 = torch.empty(shape, dtype=torch.complex128, device="cuda")
+    fb.fb_fill_uniform(plan, x0, 21)
+    u0 = torch.empty_like(x0)
+    xt = torch.empty_like(x0)
+    sums = torch.zeros((steps, 2), dtype=torch.float64, device="cuda")
+
+    def block():
+        fb.fb_fft3d_exec(plan, x0, u0, fb.FB_FORWARD)
+        for t in range(1, steps + 1):
+            fb.fb_spectral_step(plan, u0, xt, 1e-4, float(t), sums[t - 1])
+
+    block()
+    torch.cuda.synchronize()
+    want_sums, want_x = sums.clone(), xt.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        block()
+    for r in range(3):
+        xt.zero_()
+        sums.zero_()
+        other = torch.randn(1 << 16, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(sums, want_sums), r
+        assert torch.equal(xt, want_x), r
+        del other
