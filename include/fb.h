@@ -162,8 +162,8 @@ size_t fb_batch_workspace_bytes(const fb_batch *b, int in_place);
 int fb_batch_launches(const fb_batch *b);              /* launches of the per-group mode */
 const char *fb_batch_describe(const fb_batch *b);
 
-/* Executes the batch: in and out are device buffers of fb_batch_elements
- * complex64 values (equal, or not overlapping).  workspace (256-byte
+/* Executes the batch: in and out are 16-byte aligned device buffers of
+ * fb_batch_elements complex64 values (equal, or not overlapping).  workspace (256-byte
  * aligned, at least fb_batch_workspace_bytes(b, in == out) bytes) is needed
  * only in place; it may be NULL otherwise.  persistent = 1 uses the
  * persistent kernel (two launches), 0 one launch per group. */

@@ -107,6 +107,7 @@ struct AxisPlan {
     int64_t n;
     fb::RadixPlan rp;
     PassInfo pass;
+    PassInfo pass_pair;   // 16-byte pencil-pair variant (complex64 strided), when usable
     size_t tw_off;   // first entry of this axis in the plan's tables
     int64_t npencils, inner, outer, istep, stride;
     bool contig;
@@ -147,6 +148,15 @@ void build_axes(int64_t nx, int64_t ny, int64_t nz, int esize, bool mx, AxisPlan
     ax[1].npencils = nx * nz; ax[1].inner = nz;      ax[1].outer = ny * nz; ax[1].istep = 1; ax[1].stride = nz;
     // x: pencils (y, z); base = y nz + z
     ax[2].npencils = ny * nz; ax[2].inner = ny * nz; ax[2].outer = 0;       ax[2].istep = 1; ax[2].stride = ny * nz;
+    // complex64 strided passes on the vector units can move pencil pairs when
+    // pencils pair up inside each inner group
+    for (int a = 1; a < 3; a++) {
+        AxisPlan &A = ax[a];
+        A.pass_pair = PassInfo{nullptr, 0, 0, 0};
+        if (esize == 8 && !mx && A.n > 1 && A.inner % 2 == 0 && A.npencils % 2 == 0)
+            A.pass_pair = fb::find_pass_pair((int)A.n);
+    }
+    ax[0].pass_pair = PassInfo{nullptr, 0, 0, 0};
 }
 
 void describe(const AxisPlan ax[3], char *out, size_t cap)
@@ -234,6 +244,8 @@ int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, dou
 {
     const AxisPlan &A = p->ax[a];
     if (!A.pass.launch) return fail(FB_ERR_UNSUPPORTED_SIZE, "no pass for length %lld", (long long)A.n);
+    const bool pair = A.pass_pair.launch && (uintptr_t)in % 16 == 0 && (uintptr_t)out % 16 == 0;
+    const PassInfo &pi = pair ? A.pass_pair : A.pass;
     if (!pass_in_bounds(p, A)) return fail(FB_ERR_INVALID_ARG, "internal: pass geometry out of bounds");
     PassArgs args{};
     args.in = in;
@@ -254,10 +266,10 @@ int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, dou
         args.ev_lb = ev->ev_lb;
     }
     char name[96];
-    snprintf(name, sizeof name, "fft_pass<%s,n=%lld,%s%s%s>", dtype_tag(p->esize), (long long)A.n,
-             A.contig ? "contiguous" : "strided", A.pass.mx ? ",mfma" : "", ev ? ",evolve" : "");
+    snprintf(name, sizeof name, "fft_pass<%s,n=%lld,%s%s%s%s>", dtype_tag(p->esize), (long long)A.n,
+             A.contig ? "contiguous" : "strided", pi.mx ? ",mfma" : "", pair ? ",pairs" : "", ev ? ",evolve" : "");
     const double bytes = 2.0 * (double)p->N * (double)p->esize;
-    hipError_t e = timed_launch(name, bytes, st, [&] { return A.pass.launch(args, st); });
+    hipError_t e = timed_launch(name, bytes, st, [&] { return pi.launch(args, st); });
     if (e != hipSuccess) return hip_fail(e, "pass launch");
     return FB_OK;
 }
@@ -772,10 +784,11 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
             g1.args.oouter = n1;
             g1.args.oistep = 0;
             g1.args.ostride = 1;
+            g1.args.opair_step = n1;   // pencils b and b + 1 start n1 apart in the output
             g1.in_sel = 0;
             g1.out_sel = 2;   // fixed up per execution when out != in
             g1.last = 0;
-            const int P1 = fb::find_pass(esize, (int)n1, false, false).pencils_per_wg;
+            const int P1 = fb::find_pass_pair((int)n1).pencils_per_wg;
             g1.ntiles = (cnt * n2 + P1 - 1) / P1;
             // pass 2: pre-twiddle w_L^(q b), length-n2 DFTs over b < n1 (elements b + q n1)
             fb::BatchGroup g2 = new_group(n2, false);
@@ -794,7 +807,7 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
             g2.out_sel = 1;
             g2.last = 1;
             g2.inv_scale = 1.0 / (double)L;
-            const int P2 = fb::find_pass(esize, (int)n2, false, false).pencils_per_wg;
+            const int P2 = fb::find_pass_pair((int)n2).pencils_per_wg;
             g2.ntiles = (cnt * n1 + P2 - 1) / P2;
             if (!group_in_bounds(g1, segmax, b->total) || !group_in_bounds(g2, segmax, b->total))
                 e = hipErrorInvalidValue;
@@ -824,8 +837,8 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
         cols.last = 1;
         cols.phase = 1;
         cols.inv_scale = 1.0 / (double)(s * s);
-        cols.ntiles = (n2d * s + fb::find_pass(esize, (int)s, false, false).pencils_per_wg - 1) /
-                      fb::find_pass(esize, (int)s, false, false).pencils_per_wg;
+        cols.ntiles = (n2d * s + fb::find_pass_pair((int)s).pencils_per_wg - 1) /
+                      fb::find_pass_pair((int)s).pencils_per_wg;
         if (e == hipSuccess && (!group_in_bounds(rows, o2.back(), b->total) || !group_in_bounds(cols, o2.back(), b->total)))
             e = hipErrorInvalidValue;
     }
@@ -912,8 +925,8 @@ fb_status fb_batch_exec(const fb_batch *b, const void *in, void *out, void *work
                         int persistent, void *hip_stream)
 {
     if (!b) return (fb_status)fail(FB_ERR_INVALID_ARG, "batch plan is NULL");
-    if (!in || !out || (uintptr_t)in % 8 || (uintptr_t)out % 8)
-        return (fb_status)fail(FB_ERR_INVALID_ARG, "in/out must be non-NULL and 8-byte aligned");
+    if (!in || !out || (uintptr_t)in % 16 || (uintptr_t)out % 16)
+        return (fb_status)fail(FB_ERR_INVALID_ARG, "in/out must be non-NULL and 16-byte aligned");
     if (dir != FB_FORWARD && dir != FB_INVERSE)
         return (fb_status)fail(FB_ERR_INVALID_ARG, "dir must be FB_FORWARD (-1) or FB_INVERSE (+1), got %d", dir);
     const size_t bytes = (size_t)b->total * 8;
@@ -962,9 +975,10 @@ fb_status fb_batch_exec(const fb_batch *b, const void *in, void *out, void *work
         a.out = bufs.p[g.out_sel];
         a.inv = bufs.inv;
         a.scale = (bufs.inv && g.last) ? g.inv_scale : 1.0;
-        const PassInfo pi = fb::find_pass(8, g.n, g.contig != 0, false);
+        // contiguous groups move complex64 pencils, strided groups pencil pairs
+        const PassInfo pi = g.contig ? fb::find_pass(8, g.n, true, false) : fb::find_pass_pair(g.n);
         char name[96];
-        snprintf(name, sizeof name, "fft_pass<c64,n=%d,%s>", g.n, g.contig ? "contiguous" : "strided");
+        snprintf(name, sizeof name, "fft_pass<c64,n=%d,%s>", g.n, g.contig ? "contiguous" : "strided,pairs");
         e = timed_launch(name, 0.0, st, [&] { return pi.launch(a, st); });
         if (e != hipSuccess) return (fb_status)hip_fail(e, "batch pass launch");
     }

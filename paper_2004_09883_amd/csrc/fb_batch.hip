@@ -23,14 +23,16 @@ namespace fb {
 
 constexpr int max_int(int a, int b) { return a > b ? a : b; }
 
+// Contiguous tiles hold complex64 pencils; strided tiles hold pencil pairs
+// (two adjacent pencils per 16-byte element).
 template <int N> constexpr int kind_threads()
 {
-    return max_int(PassCfg<float2, N, true>::THREADS, PassCfg<float2, N, false>::THREADS);
+    return max_int(PassCfg<float2, N, true>::THREADS, PassCfg<c2x, N, false>::THREADS);
 }
-template <int N> constexpr int kind_lds()
+template <int N> constexpr int kind_lds_bytes()
 {
-    return max_int(PassCfg<float2, N, true>::P * PassCfg<float2, N, true>::LS,
-                   PassCfg<float2, N, false>::P * PassCfg<float2, N, false>::LS);
+    return max_int(PassCfg<float2, N, true>::P * PassCfg<float2, N, true>::LS * 8,
+                   PassCfg<c2x, N, false>::P * PassCfg<c2x, N, false>::LS * 16);
 }
 
 constexpr int batch_threads()
@@ -41,19 +43,19 @@ constexpr int batch_threads()
 #undef FB_MAXT
     return m;
 }
-constexpr int batch_lds_elems()
+constexpr int batch_lds_bytes()
 {
     int m = 0;
-#define FB_MAXL(L) m = max_int(m, kind_lds<L>());
+#define FB_MAXL(L) m = max_int(m, kind_lds_bytes<L>());
     FB_BATCH_KINDS(FB_MAXL)
 #undef FB_MAXL
     return m;
 }
 
 constexpr int BATCH_THREADS = batch_threads();
-constexpr int BATCH_LDS = batch_lds_elems();
+constexpr int BATCH_LDS = batch_lds_bytes() / 16;   // in 16-byte units
 static_assert(BATCH_THREADS % 64 == 0 && BATCH_THREADS <= 1024, "persistent workgroup size");
-static_assert(BATCH_LDS * 8 <= 160 * 1024, "persistent kernel LDS");
+static_assert(BATCH_LDS * 16 <= 160 * 1024, "persistent kernel LDS");
 
 int batch_persistent_threads() { return BATCH_THREADS; }
 
@@ -62,18 +64,19 @@ int batch_persistent_threads() { return BATCH_THREADS; }
 // is read through a wave-uniform pointer (scalar loads), so every branch in
 // the tile around a barrier is uniform.
 template <int L, bool CONTIG>
-__device__ __noinline__ void tile_fn(const BatchGroup *g, BatchBuffers bufs, int64_t tile, int tid, float2 *lds)
+__device__ __noinline__ void tile_fn(const BatchGroup *g, BatchBuffers bufs, int64_t tile, int tid, c2x *lds)
 {
     PassArgs a = g->args;
     a.in = bufs.p[g->in_sel];
     a.out = bufs.p[g->out_sel];
     a.inv = bufs.inv;
     a.scale = (bufs.inv && g->last) ? g->inv_scale : 1.0;
-    pass_tile<float2, L, CONTIG, false>(a, tile, tid, lds, nullptr);
+    if constexpr (CONTIG) pass_tile<float2, L, true, false>(a, tile, tid, (float2 *)lds, nullptr);
+    else pass_tile<c2x, L, false, false>(a, tile, tid, lds, nullptr);
 }
 
 __device__ __forceinline__ void run_tile(const BatchGroup *g, const BatchBuffers &bufs, int64_t tile, int tid,
-                                         float2 *lds)
+                                         c2x *lds)
 {
     switch (g->n * 2 + (g->contig ? 1 : 0)) {
 #define FB_KIND(L)                                                        \
@@ -93,7 +96,7 @@ __device__ __forceinline__ void run_tile(const BatchGroup *g, const BatchBuffers
 __global__ void __launch_bounds__(BATCH_THREADS) batch_persistent(const BatchGroup *__restrict__ groups, int g0,
                                                                   int g1, int64_t ntasks, BatchBuffers bufs)
 {
-    __shared__ float2 lds[BATCH_LDS];
+    __shared__ c2x lds[BATCH_LDS];
     const int tid = threadIdx.x;
     int g = g0;
     for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {

@@ -11,10 +11,19 @@
 
 namespace fb {
 
+// Two complex64 values of adjacent pencils, moved as one 16-byte access;
+// every operation acts on both halves (a pair of independent transforms).
+struct __attribute__((aligned(16))) c2x {
+    float2 a, b;
+};
+
 template <typename V> struct vec_traits;
-template <> struct vec_traits<double2> { using real = double; };
-template <> struct vec_traits<float2> { using real = float; };
+template <> struct vec_traits<double2> { using real = double; using tw = double2; };
+template <> struct vec_traits<float2> { using real = float; using tw = float2; };
+template <> struct vec_traits<c2x> { using real = float; using tw = float2; };
 template <typename V> using real_t = typename vec_traits<V>::real;
+// type of the twiddle factors multiplying a V
+template <typename V> using tw_t = typename vec_traits<V>::tw;
 
 template <typename V> __device__ __forceinline__ V mk(real_t<V> x, real_t<V> y) { V r; r.x = x; r.y = y; return r; }
 template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return mk<V>(a.x + b.x, a.y + b.y); }
@@ -27,6 +36,19 @@ template <typename V> __device__ __forceinline__ V cconj(V a) { return mk<V>(a.x
 template <typename V> __device__ __forceinline__ V cscale(V a, real_t<V> s) { return mk<V>(a.x * s, a.y * s); }
 // a * (-i)
 template <typename V> __device__ __forceinline__ V mul_mi(V a) { return mk<V>(a.y, -a.x); }
+
+__device__ __forceinline__ c2x mk2(float2 a, float2 b) { c2x r; r.a = a; r.b = b; return r; }
+__device__ __forceinline__ float2 mkf(float x, float y) { return make_float2(x, y); }
+__device__ __forceinline__ c2x cadd(c2x p, c2x q) { return mk2(mkf(p.a.x + q.a.x, p.a.y + q.a.y), mkf(p.b.x + q.b.x, p.b.y + q.b.y)); }
+__device__ __forceinline__ c2x csub(c2x p, c2x q) { return mk2(mkf(p.a.x - q.a.x, p.a.y - q.a.y), mkf(p.b.x - q.b.x, p.b.y - q.b.y)); }
+__device__ __forceinline__ c2x cmul(c2x p, float2 w)
+{
+    return mk2(mkf(p.a.x * w.x - p.a.y * w.y, p.a.x * w.y + p.a.y * w.x),
+               mkf(p.b.x * w.x - p.b.y * w.y, p.b.x * w.y + p.b.y * w.x));
+}
+__device__ __forceinline__ c2x cconj(c2x p) { return mk2(mkf(p.a.x, -p.a.y), mkf(p.b.x, -p.b.y)); }
+__device__ __forceinline__ c2x cscale(c2x p, float s) { return mk2(mkf(p.a.x * s, p.a.y * s), mkf(p.b.x * s, p.b.y * s)); }
+__device__ __forceinline__ c2x mul_mi(c2x p) { return mk2(mkf(p.a.y, -p.a.x), mkf(p.b.y, -p.b.x)); }
 
 // Exact-value constants of the small roots of unity (math constants, written
 // to more digits than binary64 holds; the compiler rounds them).
@@ -44,6 +66,7 @@ template <typename V> __device__ __forceinline__ V cmulc(V a, double c, double s
     const R cr = (R)c, ci = (R)s;
     return mk<V>(a.x * cr - a.y * ci, a.x * ci + a.y * cr);
 }
+__device__ __forceinline__ c2x cmulc(c2x p, double c, double s) { return cmul(p, make_float2((float)c, (float)s)); }
 
 template <typename V> __device__ __forceinline__ void dft2(V &a0, V &a1)
 {
@@ -58,9 +81,9 @@ template <typename V> __device__ __forceinline__ void dft3(V &a0, V &a1, V &a2)
     using R = real_t<V>;
     const V s = cadd(a1, a2);
     const V d = csub(a1, a2);
-    const V m = mk<V>(a0.x - (R)0.5 * s.x, a0.y - (R)0.5 * s.y);
-    // -i * S3 * d = (S3 d.y, -S3 d.x)
-    const V r = mk<V>((R)K::S3 * d.y, -(R)K::S3 * d.x);
+    const V m = csub(a0, cscale(s, (R)0.5));
+    // -i * S3 * d
+    const V r = cscale(mul_mi(d), (R)K::S3);
     a0 = cadd(a0, s);
     a1 = cadd(m, r);
     a2 = csub(m, r);

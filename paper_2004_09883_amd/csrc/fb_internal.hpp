@@ -26,6 +26,9 @@ struct PassArgs {
     // pencil b is multiplied by ptw[(q b) mod ptw_len], ptw[m] = w_L^m
     const void *ptw;
     int64_t ptw_len;
+    // pencil-pair passes: distance in elements between the outputs of the two
+    // pencils of a pair (0 = adjacent, one 16-byte store)
+    int64_t opair_step;
     int inv;            // 1: inverse (conjugate on load and on store)
     double scale;       // applied on store (1/N in the last inverse pass)
     // fused spectral evolution (contiguous passes only): element i of pencil
@@ -52,6 +55,11 @@ struct PassInfo {
 // no such variant exists).  Returns launch == nullptr when the length has no
 // instantiated pass.
 PassInfo find_pass(int esize, int n, bool contig, bool mx);
+
+// Strided complex64 pass that moves two adjacent pencils per 16-byte access
+// (needs an even number of pencils, pencil pairs adjacent in memory
+// (even `inner`) and 16-byte aligned buffers).  pencils_per_wg counts pencils.
+PassInfo find_pass_pair(int n);
 
 // Twiddle tables of one axis: for each stage s with ns > 1, entry
 // off[s] + (q-1) ns + k = w_{ns r}^(q k), w_L = exp(-2 pi i / L), in binary64

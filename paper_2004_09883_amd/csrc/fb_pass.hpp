@@ -85,6 +85,48 @@ template <typename V> __device__ __forceinline__ void st_stream(V *p, V v)
     }
 }
 
+// Element type in global memory: a pencil pair (c2x) is two adjacent
+// complex64 elements read or written with one 16-byte access.
+template <typename V> using elem_t = typename std::conditional<std::is_same<V, c2x>::value, float2, V>::type;
+
+template <typename V> __device__ __forceinline__ V ld_v(const elem_t<V> *p)
+{
+    if constexpr (std::is_same<V, c2x>::value) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        f4 r;
+        if constexpr (FB_NT) r = __builtin_nontemporal_load((const f4 *)p);
+        else r = *(const f4 *)p;
+        return mk2(make_float2(r.x, r.y), make_float2(r.z, r.w));
+    } else {
+        return ld_stream(p);
+    }
+}
+template <typename V> __device__ __forceinline__ void st_v(elem_t<V> *p, V v)
+{
+    if constexpr (std::is_same<V, c2x>::value) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        f4 r;
+        r.x = v.a.x; r.y = v.a.y; r.z = v.b.x; r.w = v.b.y;
+        if constexpr (FB_NT) __builtin_nontemporal_store(r, (f4 *)p);
+        else *(f4 *)p = r;
+    } else {
+        st_stream(p, v);
+    }
+}
+
+// Pre-twiddle of element e of local pencil lp (and lp + 1 for a pair).
+template <typename V> __device__ __forceinline__ V pre_twiddle(V v, int64_t e, int64_t lp, const void *ptw, int64_t L)
+{
+    const tw_t<V> *t = (const tw_t<V> *)ptw;
+    if constexpr (std::is_same<V, c2x>::value) {
+        v.a = cmul(v.a, t[(e * lp) % L]);
+        v.b = cmul(v.b, t[(e * (lp + 1)) % L]);
+        return v;
+    } else {
+        return cmul(v, t[(e * lp) % L]);
+    }
+}
+
 template <typename V, int N, bool CONTIG, bool MX> struct MxStage {
     // whether stage s runs on the matrix cores
     static constexpr bool at(int s) { return MX && PassCfg<V, N, CONTIG>::RP.r[s] == 16; }
@@ -206,11 +248,15 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
     constexpr int T = Cfg::T, P = Cfg::P, M = Cfg::M, LS = Cfg::LS;
     constexpr int NST = RP.count;
     static_assert(!MX || mx_capable<V, N, CONTIG>(), "no matrix-core variant for this pass");
+    constexpr bool PAIR = std::is_same<V, c2x>::value;   // each unit is two adjacent pencils
+    static_assert(!PAIR || (!CONTIG && !MX), "pencil pairs are for strided vector-unit passes");
+    using E = elem_t<V>;
+    using TW = tw_t<V>;
 
     const bool active = tid < Cfg::THREADS;
     const int t = CONTIG ? tid % T : tid / P;
     const int pp = CONTIG ? tid / T : tid % P;
-    const int64_t p = tile * P + pp;
+    const int64_t p = (tile * P + pp) * (PAIR ? 2 : 1);   // (first) pencil of this thread
     const bool valid = active && p < a.npencils;
     int64_t seg0 = 0, lp = p;   // segment start and local pencil index
     if (a.seg_off && valid) {
@@ -220,9 +266,9 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
     const int64_t base = valid ? seg0 + (lp / a.inner) * a.outer + (lp % a.inner) * a.istep : 0;
     const bool ogeom = a.ostride != 0;
     const int64_t obase = !valid ? 0 : ogeom ? seg0 + (lp / a.oinner) * a.oouter + (lp % a.oinner) * a.oistep : base;
-    const V *__restrict__ gin = (const V *)a.in + base;
-    V *__restrict__ gout = (V *)a.out + obase;
-    const V *__restrict__ tw = (const V *)a.tw;
+    const E *__restrict__ gin = (const E *)a.in + base;
+    E *__restrict__ gout = (E *)a.out + obase;
+    const TW *__restrict__ tw = (const TW *)a.tw;
     const int64_t S = a.stride;
     const int64_t OS = ogeom ? a.ostride : a.stride;
     V *row = lds + (active ? pp : 0) * LS;
@@ -261,7 +307,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                 const int b = t + T * u;
                 if (NBF % T == 0 || b < NBF) {
 #pragma unroll
-                    for (int q = 0; q < R0; q++) v[u * R0 + q] = ld_stream(gin + (int64_t)(b + q * NBF) * S);
+                    for (int q = 0; q < R0; q++) v[u * R0 + q] = ld_v<V>(gin + (int64_t)(b + q * NBF) * S);
                 }
             }
             if constexpr (CONTIG) {
@@ -282,7 +328,6 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
             }
             // pre-twiddle after the conjugation: an inverse is conj(DFT(conj(x))) as a whole
             if (a.ptw) {
-                const V *__restrict__ ptw = (const V *)a.ptw;
 #pragma unroll
                 for (int u = 0; u < U; u++) {
                     const int b = t + T * u;
@@ -290,7 +335,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
 #pragma unroll
                         for (int q = 0; q < R0; q++) {
                             const int64_t e = b + q * NBF;
-                            if (e > 0) v[u * R0 + q] = cmul(v[u * R0 + q], ptw[(e * lp) % a.ptw_len]);
+                            if (e > 0) v[u * R0 + q] = pre_twiddle(v[u * R0 + q], e, lp, a.ptw, a.ptw_len);
                         }
                     }
                 }
@@ -437,7 +482,14 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                         V o = v[u * RL + q];
                         if (a.inv) o = cconj(o);
                         if (a.scale != 1.0) o = cscale(o, sc);
-                        st_stream(gout + (int64_t)(b + q * NBF) * OS, o);
+                        if constexpr (PAIR) {
+                            if (a.opair_step) {   // the pair's outputs are not adjacent
+                                st_stream(gout + (int64_t)(b + q * NBF) * OS, o.a);
+                                st_stream(gout + (int64_t)(b + q * NBF) * OS + a.opair_step, o.b);
+                                continue;
+                            }
+                        }
+                        st_v<V>(gout + (int64_t)(b + q * NBF) * OS, o);
                     }
                 }
             }

@@ -1,4 +1,5 @@
-// Pencil passes for complex64 grids (binary32 arithmetic).
+// Pencil passes for complex64 grids (binary32 arithmetic; the matrix-core
+// variants of the radix-16 stages included).
 #include "fb_pass_inst.hpp"
 
 namespace fb {

@@ -10,7 +10,8 @@ namespace fb {
 template <typename V, int N, bool CONTIG, bool MX> hipError_t launch_pass(const PassArgs &a, hipStream_t st)
 {
     using Cfg = PassCfg<V, N, CONTIG>;
-    const int64_t blocks = (a.npencils + Cfg::P - 1) / Cfg::P;
+    constexpr int64_t UNIT = std::is_same<V, c2x>::value ? 2 : 1;   // pencils per tile slot
+    const int64_t blocks = (a.npencils + UNIT * Cfg::P - 1) / (UNIT * Cfg::P);
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL((fft_pass<V, N, CONTIG, MX>), dim3((unsigned)blocks), dim3(Cfg::THREADS), 0, st, a);
     return hipGetLastError();
@@ -35,6 +36,23 @@ template <typename V, int N> PassInfo pass_info(bool contig, bool mx)
 #define FB_FOR_EACH_LENGTH(X) \
     X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) \
     X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096)
+
+// Strided complex64 passes over pencil pairs (16-byte accesses).
+template <int N> PassInfo pass_info_pair()
+{
+    using Cfg = PassCfg<c2x, N, false>;
+    return {&launch_pass<c2x, N, false, false>, 2 * Cfg::P, Cfg::THREADS, 0};
+}
+
+inline PassInfo find_pass_pair_t(int n)
+{
+    switch (n) {
+#define FB_CASE(L) case L: return pass_info_pair<L>();
+        FB_FOR_EACH_LENGTH(FB_CASE)
+#undef FB_CASE
+    default: return {nullptr, 0, 0, 0};
+    }
+}
 
 template <typename V> PassInfo find_pass_t(int n, bool contig, bool mx)
 {
