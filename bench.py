@@ -86,36 +86,78 @@ def cpu_baseline(budget_steps: int = 10) -> dict:
                       f"{SHAPE[0]}x{SHAPE[1]}x{SHAPE[2]} complex128 block ({dt:.2f} s wall)"}
 
 
-def forms_section(torch, fb, reps: int = 20) -> dict:
-    """512 x 256 x 256 forward 3D FFT per form: time, GFLOP/s, %roofline."""
+def forms_section(torch, fb, reps: int = 20, steps: int = 10) -> dict:
+    """512 x 256 x 256 grid of N(0,1) entries (Box-Muller, seed 2; the
+    complex64 forms get the values rounded to complex64): per form the
+    forward 3D FFT and one fused spectral step (evolve + inverse FFT +
+    checksum), time, GFLOP/s and %roofline, and the relative L2 error of the
+    forward spectrum and of x_t at t = ``steps`` against the complex128 path
+    (itself within 1e-15 of the binary64 oracle in the tests)."""
+    from paper_2004_09883_amd import inputs
+
     shape = (512, 256, 256)
     n = math.prod(shape)
+    host = torch.from_numpy(inputs.gaussian_grid(shape, 2))
     out = {}
+    ref = {}
+
+    def rel_l2(a, b):
+        d = (a.to(torch.complex128) - b).abs().pow(2).sum().sqrt()
+        return float(d / b.abs().pow(2).sum().sqrt())
+
     for name, dt, esize in (("c128", fb.FB_C128, 16), ("c64", fb.FB_C64, 8),
                             ("c64_splitbf16", fb.FB_C64_SPLITBF16, 8)):
         plan = fb.Plan(*shape, dt)
-        x = torch.empty(shape, dtype=plan.torch_dtype, device="cuda")
-        y = torch.empty_like(x)
-        fb.fb_fill_uniform(plan, x, 2)
+        x = host.to(plan.torch_dtype).cuda()
+        u = torch.empty_like(x)
+        xt = torch.empty_like(x)
+        sums = torch.zeros(2, dtype=torch.float64, device="cuda")
         for _ in range(3):
-            fb.fb_fft3d_exec(plan, x, y, fb.FB_FORWARD)
+            fb.fb_fft3d_exec(plan, x, u, fb.FB_FORWARD)
         torch.cuda.synchronize()
         s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         s.record()
         for _ in range(reps):
-            fb.fb_fft3d_exec(plan, x, y, fb.FB_FORWARD)
+            fb.fb_fft3d_exec(plan, x, u, fb.FB_FORWARD)
         e.record()
         torch.cuda.synchronize()
         ms = s.elapsed_time(e) / reps
+        s.record()
+        for _ in range(reps):
+            fb.fb_spectral_step(plan, u, xt, ALPHA, float(steps), sums)
+        e.record()
+        torch.cuda.synchronize()
+        ms_step = s.elapsed_time(e) / reps
+        # per-pass durations of the forward transform (separate, profiled loop)
+        fb.fb_profile_enable(True)
+        for _ in range(5):
+            fb.fb_fft3d_exec(plan, x, u, fb.FB_FORWARD)
+        torch.cuda.synchronize()
+        passes = [{"kernel": k["kernel"], "avg_ms": round(k["avg_ms"], 5),
+                   "gbs": round(k["bytes_per_launch"] / (k["avg_ms"] * 1e-3) / 1e9, 1)}
+                  for k in fb.fb_profile_report()]
+        fb.fb_profile_enable(False)
         b_alg = 3 * 2 * esize * n
-        out[name] = {"forward_ms": round(ms, 4), "gflops": round(flops_fft(shape) / ms / 1e6, 1),
-                     "hbm_roofline_frac": round(b_alg / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
-                     "model_bytes": b_alg}
-        del x, y, plan
+        rec = {"forward_ms": round(ms, 4), "gflops": round(flops_fft(shape) / ms / 1e6, 1),
+               "hbm_roofline_frac": round(b_alg / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+               "step_ms": round(ms_step, 4),
+               "step_hbm_roofline_frac": round(b_alg / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+               "model_bytes": b_alg, "passes": passes}
+        if name == "c128":
+            ref["u"] = u.clone()
+            ref["x"] = xt.clone()
+        else:
+            rec["rel_l2_forward_vs_c128"] = float("%.3g" % rel_l2(u, ref["u"]))
+            rec["rel_l2_step%d_vs_c128" % steps] = float("%.3g" % rel_l2(xt, ref["x"]))
+        out[name] = rec
+        del x, u, xt, plan
         torch.cuda.empty_cache()
     out["c64_speedup_vs_c128"] = round(out["c128"]["forward_ms"] / out["c64"]["forward_ms"], 3)
     out["c64_splitbf16_speedup_vs_c128"] = round(out["c128"]["forward_ms"] / out["c64_splitbf16"]["forward_ms"], 3)
-    out["workload"] = "forward 3D FFT of a 512x256x256 grid, 3 pencil passes"
+    out["workload"] = ("512x256x256 grid, N(0,1) entries (Box-Muller, seed 2): forward 3D FFT (3 pencil passes) "
+                       "and one spectral step at t=%d, alpha=1e-6" % steps)
+    del ref
+    torch.cuda.empty_cache()
     return out
 
 
@@ -236,6 +278,8 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="measured duration of the serving run (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate of the serving run")
+    ap.add_argument("--serve-sweep", type=float, default=3.0,
+                    help="seconds per rate of the 500/1000/1500 req/s context sweep (0: skip)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain 512 MiB copy (counter calibration)")
     args = ap.parse_args()
@@ -260,9 +304,9 @@ def main() -> int:
     plan = fb.Plan(*SHAPE, fb.FB_C128)
     x0 = torch.empty(SHAPE, dtype=torch.complex128, device="cuda")
     u0 = torch.empty_like(x0)
-    xt = torch.empty_like(x0)
     sums = torch.zeros((T_STEPS, 2), dtype=torch.float64, device="cuda")
     fb.fb_fill_uniform(plan, x0, SEED)
+    xt = torch.empty_like(x0)
 
     def step():
         fb.fb_fft3d_exec(plan, x0, u0, fb.FB_FORWARD)
@@ -307,13 +351,27 @@ def main() -> int:
     wall = time.perf_counter() - t_wall
 
     ms = start.elapsed_time(stop) / args.steps
+
+    # the same block started cold: a 512 MiB write before each block evicts
+    # the grids from the 256 MB last-level cache (the write is not timed)
+    flush = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")
+    cold = 0.0
+    for _ in range(args.steps):
+        flush.fill_(1)
+        start.record()
+        run()
+        stop.record()
+        torch.cuda.synchronize()
+        cold += start.elapsed_time(stop)
+    cold_ms = cold / args.steps
+    del flush
+
     flops_step = (1 + T_STEPS) * flops_fft(SHAPE)
     value = flops_step / (ms * 1e-3) / 1e9
     c = sums.cpu().numpy()
     if not all(map(math.isfinite, c.reshape(-1))):
         print("non-finite checksum", file=sys.stderr)
         return 1
-
     passes = [k for k in prof if k["kernel"].startswith("fft_pass")]
     dom = max(passes, key=lambda k: k["total_ms"])
     achieved = dom["bytes_per_launch"] / (dom["avg_ms"] * 1e-3) / 1e9
@@ -330,7 +388,8 @@ def main() -> int:
                       "shape": list(SHAPE), "steps_per_block": T_STEPS, "alpha": ALPHA,
                       "transforms_per_step": 1 + T_STEPS, "wall_s": round(wall, 3),
                       "launch": "hip graph (one replay per step)" if graph is not None else "eager",
-                      "eager_ms_per_step": round(eager_ms, 4)},
+                      "eager_ms_per_step": round(eager_ms, 4),
+                      "cache_flushed_ms_per_step": round(cold_ms, 4)},
            "roofline": roofline,
            "kernels": [{k: v for k, v in p.items()} for p in prof]}
     if not args.no_forms:
@@ -341,6 +400,14 @@ def main() -> int:
     if args.serve_seconds > 0:
         from paper_2004_09883_amd import serve
         rec["serving"] = serve.run_serving(rate=args.serve_rate, duration=args.serve_seconds, warmup=1.0)
+        if args.serve_sweep > 0:
+            keys = ("throughput_req_s", "model_gbs", "offered_load_rho", "saturated", "p50_ms", "p99_ms",
+                    "queue_wait_p99_ms", "service_p50_ms", "service_p99_ms")
+            sweep = {}
+            for rate in (500.0, 1000.0, 1500.0):
+                r = serve.run_serving(rate=rate, duration=args.serve_sweep, warmup=1.0)
+                sweep[str(int(rate))] = {k: r[k] for k in keys}
+            rec["serving"]["rate_sweep"] = sweep
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline()
         if "paper_2d_2048" in rec:

@@ -134,6 +134,16 @@ fb_status fb_spectral_step(const fb_plan *p, const void *uhat0, void *x_out, dou
  * the binary64 values rounded to nearest). */
 fb_status fb_fill_uniform(const fb_plan *p, void *x, uint64_t seed, void *hip_stream);
 
+/* Forward 3D DFT (FB_FORWARD, unnormalized) of the grid fb_fill_uniform(p,
+ * ., seed) would write, into `out`, with the input generated inside the
+ * first pencil pass instead of being written to and read back from device
+ * memory: the result equals fb_fill_uniform followed by fb_fft3d_exec
+ * bit for bit.  The paper replaces a detected block (here: make the input,
+ * transform it) by one library call of the same meaning (section 3.4, B-1).
+ * `out` is a device grid of the plan's dtype, aligned to its element size.
+ * Errors as fb_fft3d_exec. */
+fb_status fb_fft3d_forward_uniform(const fb_plan *p, uint64_t seed, void *out, void *hip_stream);
+
 /* ---- Batched form ------------------------------------------------------
  * Many independent complex64 transforms in one call: n1d 1D transforms of
  * lengths lens[0..n1d) (each 2^a or 3*2^a, 2 <= n <= 2^21) and n2d 2D
@@ -177,8 +187,9 @@ fb_status fb_batch_exec(const fb_batch *b, const void *in, void *out, void *work
  * checksums) fit in the HBM budget, so work of requests that arrive while
  * others run overlaps on the device.  Plans (per shape and dtype) and device
  * buffers (per size) stay resident; pooled buffers count against the budget.
- * A request: its input grid is generated on the device from the stream seed
- * SplitMix64(seed, request_key) (as fb_fill_uniform), transformed forward,
+ * A request: its input grid (as fb_fill_uniform with the stream seed
+ * SplitMix64(seed, request_key)) is generated inside the first forward
+ * pass (fb_fft3d_forward_uniform) and transformed forward,
  * then for t = 1..steps evolved (alpha, t), transformed back and
  * checksummed; the checksums (and the final grid when want_grid) come back
  * to host memory.  A result does not depend on what else runs. */

@@ -148,13 +148,16 @@ void build_axes(int64_t nx, int64_t ny, int64_t nz, int esize, bool mx, AxisPlan
     ax[1].npencils = nx * nz; ax[1].inner = nz;      ax[1].outer = ny * nz; ax[1].istep = 1; ax[1].stride = nz;
     // x: pencils (y, z); base = y nz + z
     ax[2].npencils = ny * nz; ax[2].inner = ny * nz; ax[2].outer = 0;       ax[2].istep = 1; ax[2].stride = ny * nz;
-    // complex64 strided passes on the vector units can move pencil pairs when
-    // pencils pair up inside each inner group
+    // complex64 strided passes can move pencil pairs when pencils pair up
+    // inside each inner group; the pair pass must run its radix-16 stages on
+    // the same units as the single-pencil pass of the plan
     for (int a = 1; a < 3; a++) {
         AxisPlan &A = ax[a];
         A.pass_pair = PassInfo{nullptr, 0, 0, 0};
-        if (esize == 8 && !mx && A.n > 1 && A.inner % 2 == 0 && A.npencils % 2 == 0)
-            A.pass_pair = fb::find_pass_pair((int)A.n);
+        if (esize == 8 && A.n > 1 && A.inner % 2 == 0 && A.npencils % 2 == 0 && A.pass.launch) {
+            const PassInfo pp = fb::find_pass_pair((int)A.n, A.pass.mx != 0);
+            if (pp.launch && pp.mx == A.pass.mx) A.pass_pair = pp;
+        }
     }
     ax[0].pass_pair = PassInfo{nullptr, 0, 0, 0};
 }
@@ -240,7 +243,7 @@ bool pass_in_bounds(const fb_plan *p, const AxisPlan &A)
 }
 
 int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, double scale, const PassArgs *ev,
-                hipStream_t st)
+                hipStream_t st, const uint64_t *gen_seed = nullptr)
 {
     const AxisPlan &A = p->ax[a];
     if (!A.pass.launch) return fail(FB_ERR_UNSUPPORTED_SIZE, "no pass for length %lld", (long long)A.n);
@@ -265,10 +268,16 @@ int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, dou
         args.ev_la = ev->ev_la;
         args.ev_lb = ev->ev_lb;
     }
+    if (gen_seed) {
+        args.gen = 1;
+        args.gen_seed = *gen_seed;
+    }
     char name[96];
-    snprintf(name, sizeof name, "fft_pass<%s,n=%lld,%s%s%s%s>", dtype_tag(p->esize), (long long)A.n,
-             A.contig ? "contiguous" : "strided", pi.mx ? ",mfma" : "", pair ? ",pairs" : "", ev ? ",evolve" : "");
-    const double bytes = 2.0 * (double)p->N * (double)p->esize;
+    snprintf(name, sizeof name, "fft_pass<%s,n=%lld,%s%s%s%s%s>", dtype_tag(p->esize), (long long)A.n,
+             A.contig ? "contiguous" : "strided", pi.mx ? ",mfma" : "", pair ? ",pairs" : "", ev ? ",evolve" : "",
+             gen_seed ? ",generated-input" : "");
+    // a pass with generated input only writes the grid
+    const double bytes = (gen_seed ? 1.0 : 2.0) * (double)p->N * (double)p->esize;
     hipError_t e = timed_launch(name, bytes, st, [&] { return pi.launch(args, st); });
     if (e != hipSuccess) return hip_fail(e, "pass launch");
     return FB_OK;
@@ -278,7 +287,7 @@ int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, dou
 // ones work in place on `out`.  `ev` (optional) fuses the evolution into the
 // first pass, which must then be the contiguous z pass.
 int run_passes(const fb_plan *p, const void *in, void *out, int dir, const PassArgs *ev, hipStream_t st,
-               int axes = 7)
+               int axes = 7, const uint64_t *gen_seed = nullptr)
 {
     int last = -1;
     double nsel = 1.0;
@@ -288,6 +297,11 @@ int run_passes(const fb_plan *p, const void *in, void *out, int dir, const PassA
             nsel *= (double)p->ax[a].n;
         }
     if (last < 0) {
+        if (gen_seed) {   // a 1x1x1 grid: the transform is the identity
+            hipError_t e = fb::launch_fill_uniform(p->esize, out, p->N, *gen_seed, st);
+            if (e != hipSuccess) return hip_fail(e, "fill launch");
+            return FB_OK;
+        }
         if (in != out) {
             hipError_t e = hipMemcpyAsync(out, in, (size_t)p->N * (size_t)p->esize, hipMemcpyDeviceToDevice, st);
             if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
@@ -298,7 +312,8 @@ int run_passes(const fb_plan *p, const void *in, void *out, int dir, const PassA
     for (int a = 0; a < 3; a++) {
         if (!(axes >> a & 1) || p->ax[a].n <= 1) continue;
         const double scale = (dir > 0 && a == last) ? 1.0 / nsel : 1.0;
-        int rc = launch_axis(p, a, first ? in : out, out, dir > 0, scale, first ? ev : nullptr, st);
+        int rc = launch_axis(p, a, first ? in : out, out, dir > 0, scale, first ? ev : nullptr, st,
+                             first ? gen_seed : nullptr);
         if (rc) return rc;
         first = false;
     }
@@ -554,6 +569,15 @@ fb_status fb_spectral_step(const fb_plan *p, const void *uhat0, void *x_out, dou
     return (fb_status)ok();
 }
 
+fb_status fb_fft3d_forward_uniform(const fb_plan *p, uint64_t seed, void *out, void *hip_stream)
+{
+    if (check_plan(p) || check_grid_ptr(p, out, "out")) return (fb_status)g_code;
+    if (check_device(p)) return (fb_status)g_code;
+    // the first pass generates its input; `in` is never read, `out` stands in
+    if (run_passes(p, out, out, FB_FORWARD, nullptr, (hipStream_t)hip_stream, 7, &seed)) return (fb_status)g_code;
+    return (fb_status)ok();
+}
+
 fb_status fb_fill_uniform(const fb_plan *p, void *x, uint64_t seed, void *hip_stream)
 {
     if (check_plan(p) || check_grid_ptr(p, x, "x")) return (fb_status)g_code;
@@ -586,7 +610,8 @@ struct fb_batch {
     fb::BatchGroup *groups_dev;
     std::vector<void *> dev_allocs;  // tables, segment offsets
     int device;
-    int nblocks;                     // persistent grid
+    int nblocks[2];                  // persistent grid per phase
+    int lds_bytes[2];                // persistent LDS per phase: the largest tile kind of the phase
     std::string desc;
 };
 
@@ -790,6 +815,10 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
             g1.last = 0;
             const int P1 = fb::find_pass_pair((int)n1).pencils_per_wg;
             g1.ntiles = (cnt * n2 + P1 - 1) / P1;
+            // a tile's outputs (pencils b .. b + P1 - 1 of one transform) form one
+            // block of P1 n1 elements: write it whole when tiles do not straddle
+            // transforms
+            g1.args.otile = (n2 % P1 == 0) ? 1 : 0;
             // pass 2: pre-twiddle w_L^(q b), length-n2 DFTs over b < n1 (elements b + q n1)
             fb::BatchGroup g2 = new_group(n2, false);
             set_geom(g2.args, cnt * n1, n1, soff, n1, 0, 1, n1);
@@ -809,7 +838,9 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
             g2.inv_scale = 1.0 / (double)L;
             const int P2 = fb::find_pass_pair((int)n2).pencils_per_wg;
             g2.ntiles = (cnt * n1 + P2 - 1) / P2;
-            if (!group_in_bounds(g1, segmax, b->total) || !group_in_bounds(g2, segmax, b->total))
+            // the pass-2 kernel indexes the root table by q b < n2 n1 without a reduction
+            if (!group_in_bounds(g1, segmax, b->total) || !group_in_bounds(g2, segmax, b->total) ||
+                g2.args.ptw_len < n2 * g2.args.seg_pencils)
                 e = hipErrorInvalidValue;
             g2.phase = 1;
             pass1.push_back(g1);
@@ -874,8 +905,17 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
     b->groups_dev = dev_alloc<fb::BatchGroup>(b, b->groups.size(), e);
     if (e == hipSuccess)
         e = hipMemcpy(b->groups_dev, b->groups.data(), b->groups.size() * sizeof(fb::BatchGroup), hipMemcpyHostToDevice);
-    int per_cu = 0, cus = 0;
-    if (e == hipSuccess) e = fb::batch_occupancy(&per_cu);
+    int per_cu[2] = {0, 0}, cus = 0;
+    for (int ph = 0; ph < 2; ph++) {
+        b->lds_bytes[ph] = 16;
+        for (auto &g : b->groups)
+            if (g.phase == ph) {
+                const int lb = fb::batch_kind_lds_bytes(g.n, g.contig != 0);
+                if (lb < 0) e = hipErrorInvalidValue;
+                if (lb > b->lds_bytes[ph]) b->lds_bytes[ph] = lb;
+            }
+        if (e == hipSuccess) e = fb::batch_occupancy(b->lds_bytes[ph], &per_cu[ph]);
+    }
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -884,11 +924,12 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
         delete b;
         return nullptr;
     }
-    b->nblocks = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    for (int ph = 0; ph < 2; ph++) b->nblocks[ph] = (per_cu[ph] > 0 ? per_cu[ph] : 1) * (cus > 0 ? cus : 1);
     char d[256];
-    snprintf(d, sizeof d, "batch n1d=%d n2d=%d side=%lld groups=%d tiles=%lld+%lld elements=%lld", n1d, n2d,
-             (long long)side2d, (int)b->groups.size(), (long long)b->ntasks[0], (long long)b->ntasks[1],
-             (long long)b->total);
+    snprintf(d, sizeof d,
+             "batch n1d=%d n2d=%d side=%lld groups=%d tiles=%lld+%lld elements=%lld persistent grid=%d+%d lds=%d+%d",
+             n1d, n2d, (long long)side2d, (int)b->groups.size(), (long long)b->ntasks[0], (long long)b->ntasks[1],
+             (long long)b->total, b->nblocks[0], b->nblocks[1], b->lds_bytes[0], b->lds_bytes[1]);
     b->desc = d;
     ok();
     return b;
@@ -959,12 +1000,13 @@ fb_status fb_batch_exec(const fb_batch *b, const void *in, void *out, void *work
     if (persistent) {
         const int ng = (int)b->groups.size();
         e = timed_launch("batch_persistent<c64,phase0>", 0.0, st, [&] {
-            return fb::launch_batch_persistent(b->groups_dev, 0, b->phase1_begin, b->ntasks[0], b->nblocks, bufs, st);
+            return fb::launch_batch_persistent(b->groups_dev, 0, b->phase1_begin, b->ntasks[0], b->nblocks[0],
+                                               b->lds_bytes[0], bufs, st);
         });
         if (e == hipSuccess)
             e = timed_launch("batch_persistent<c64,phase1>", 0.0, st, [&] {
-                return fb::launch_batch_persistent(b->groups_dev, b->phase1_begin, ng, b->ntasks[1], b->nblocks, bufs,
-                                                   st);
+                return fb::launch_batch_persistent(b->groups_dev, b->phase1_begin, ng, b->ntasks[1], b->nblocks[1],
+                                                   b->lds_bytes[1], bufs, st);
             });
         if (e != hipSuccess) return (fb_status)hip_fail(e, "persistent batch launch");
         return (fb_status)ok();

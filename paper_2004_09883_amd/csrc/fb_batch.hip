@@ -53,19 +53,36 @@ constexpr int batch_lds_bytes()
 }
 
 constexpr int BATCH_THREADS = batch_threads();
-constexpr int BATCH_LDS = batch_lds_bytes() / 16;   // in 16-byte units
+constexpr int BATCH_LDS_MAX = batch_lds_bytes();
 static_assert(BATCH_THREADS % 64 == 0 && BATCH_THREADS <= 1024, "persistent workgroup size");
-static_assert(BATCH_LDS * 16 <= 160 * 1024, "persistent kernel LDS");
+static_assert(BATCH_LDS_MAX <= 160 * 1024, "persistent kernel LDS");
 
 int batch_persistent_threads() { return BATCH_THREADS; }
 
-// Each tile kind is compiled as a function of its own, so that the register
-// allocation of one kind does not burden the others.  The group descriptor
-// is read through a wave-uniform pointer (scalar loads), so every branch in
-// the tile around a barrier is uniform.
-template <int L, bool CONTIG>
-__device__ __noinline__ void tile_fn(const BatchGroup *g, BatchBuffers bufs, int64_t tile, int tid, c2x *lds)
+int batch_kind_lds_bytes(int n, bool contig)
 {
+    switch (n) {
+#define FB_KL(L)                                                                                          \
+    case L:                                                                                                \
+        return contig ? PassCfg<float2, L, true>::P * PassCfg<float2, L, true>::LS * 8                   \
+                      : PassCfg<c2x, L, false>::P * PassCfg<c2x, L, false>::LS * 16;
+        FB_BATCH_KINDS(FB_KL)
+#undef FB_KL
+    default: return -1;
+    }
+}
+
+// One tile of one group.  Every kind is inlined into the switch below; the
+// empty asm statement makes `tid` opaque inside each case, which keeps the
+// compiler from hoisting every kind's index arithmetic in front of the
+// switch (that would keep all of it live at once: the registers of the
+// kernel are then those of its largest kind instead of their sum).  The
+// group descriptor is read through a wave-uniform pointer (scalar loads), so
+// every branch around a barrier is uniform.
+template <int L, bool CONTIG>
+__device__ __forceinline__ void tile_fn(const BatchGroup *g, const BatchBuffers &bufs, int64_t tile, int tid, c2x *lds)
+{
+    asm volatile("" : "+v"(tid));
     PassArgs a = g->args;
     a.in = bufs.p[g->in_sel];
     a.out = bufs.p[g->out_sel];
@@ -92,11 +109,12 @@ __device__ __forceinline__ void run_tile(const BatchGroup *g, const BatchBuffers
 // numbered 0 .. ntasks-1 in group order and workgroup w takes tiles
 // w, w + gridDim.x, w + 2 gridDim.x, ...  Groups of one phase are independent
 // of each other; a phase that depends on another is launched after it on the
-// same stream.  There is no communication between workgroups.
+// same stream.  There is no communication between workgroups.  The LDS is
+// dynamic, sized by the host for the largest tile kind of the phase.
 __global__ void __launch_bounds__(BATCH_THREADS) batch_persistent(const BatchGroup *__restrict__ groups, int g0,
                                                                   int g1, int64_t ntasks, BatchBuffers bufs)
 {
-    __shared__ c2x lds[BATCH_LDS];
+    extern __shared__ c2x lds[];
     const int tid = threadIdx.x;
     int g = g0;
     for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
@@ -107,18 +125,20 @@ __global__ void __launch_bounds__(BATCH_THREADS) batch_persistent(const BatchGro
 }
 
 hipError_t launch_batch_persistent(const BatchGroup *groups_dev, int g0, int g1, int64_t ntasks, int nblocks,
-                                   const BatchBuffers &bufs, hipStream_t st)
+                                   int lds_bytes, const BatchBuffers &bufs, hipStream_t st)
 {
     if (ntasks <= 0) return hipSuccess;
+    if (lds_bytes <= 0 || lds_bytes > BATCH_LDS_MAX) return hipErrorInvalidValue;
     const int64_t blocks = ntasks < nblocks ? ntasks : nblocks;
-    hipLaunchKernelGGL(batch_persistent, dim3((unsigned)blocks), dim3(BATCH_THREADS), 0, st, groups_dev, g0, g1,
-                       ntasks, bufs);
+    hipLaunchKernelGGL(batch_persistent, dim3((unsigned)blocks), dim3(BATCH_THREADS), (unsigned)lds_bytes, st,
+                       groups_dev, g0, g1, ntasks, bufs);
     return hipGetLastError();
 }
 
-hipError_t batch_occupancy(int *blocks_per_cu)
+hipError_t batch_occupancy(int lds_bytes, int *blocks_per_cu)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent, BATCH_THREADS, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent, BATCH_THREADS,
+                                                        (size_t)lds_bytes);
 }
 
 }  // namespace fb

@@ -31,9 +31,12 @@ struct BatchBuffers {
 };
 
 int batch_persistent_threads();
-hipError_t batch_occupancy(int *blocks_per_cu);
+// LDS bytes of one tile of the persistent kernel for a group of pass length
+// n (-1 when n is not a tile kind)
+int batch_kind_lds_bytes(int n, bool contig);
+hipError_t batch_occupancy(int lds_bytes, int *blocks_per_cu);
 hipError_t launch_batch_persistent(const BatchGroup *groups_dev, int g0, int g1, int64_t ntasks, int nblocks,
-                                   const BatchBuffers &bufs, hipStream_t st);
+                                   int lds_bytes, const BatchBuffers &bufs, hipStream_t st);
 
 // tables[m] = w_n^m = exp(-2 pi i m / n), m < n, binary64 and binary32
 hipError_t launch_roots(int64_t n, double2 *t64, float2 *t32, hipStream_t st);

@@ -164,6 +164,34 @@ template <typename R> __device__ __forceinline__ R evol_factor(double c, double 
     else return expf(-(float)c * (float)k2);
 }
 
+// SplitMix64 (Steele, Lea, Flood 2014) at counter c of stream `seed`:
+// the (c+1)-th output of the sequential generator started at state `seed`.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c)
+{
+    uint64_t z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Uniform on [-1, 1) from the top 53 bits (exact in binary64).
+__device__ __forceinline__ double u_pm1(uint64_t h) { return (double)(h >> 11) * 0x1.0p-52 - 1.0; }
+
+// Element i of the seeded uniform grid: re = U(seed, 2i), im = U(seed, 2i+1),
+// rounded to the element's precision; a pencil pair holds elements i, i + 1.
+template <typename V> __device__ __forceinline__ V uniform_elem(uint64_t seed, uint64_t i)
+{
+    if constexpr (std::is_same<V, c2x>::value) {
+        return mk2(uniform_elem<float2>(seed, i), uniform_elem<float2>(seed, i + 1));
+    } else {
+        using R = real_t<V>;
+        V v;
+        v.x = (R)u_pm1(splitmix64_at(seed, 2 * i));
+        v.y = (R)u_pm1(splitmix64_at(seed, 2 * i + 1));
+        return v;
+    }
+}
+
 template <int B, int E, typename F> __device__ __forceinline__ void static_for(F &&f)
 {
     if constexpr (B < E) {

@@ -23,12 +23,24 @@ struct PassArgs {
     const int64_t *seg_off;
     int64_t seg_pencils;
     // pre-twiddle on load (two-pass long transforms): element q of local
-    // pencil b is multiplied by ptw[(q b) mod ptw_len], ptw[m] = w_L^m
+    // pencil b is multiplied by ptw[q b], ptw[m] = w_L^m; requires
+    // ptw_len >= N seg_pencils so that q b never leaves the table
     const void *ptw;
     int64_t ptw_len;
     // pencil-pair passes: distance in elements between the outputs of the two
     // pencils of a pair (0 = adjacent, one 16-byte store)
     int64_t opair_step;
+    // tile-contiguous output (strided passes): the outputs of the P pencils
+    // of a tile fill one contiguous block, element k of tile pencil j at
+    // obase(first pencil) + j N + k; the tile is then written from LDS with
+    // consecutive lanes on consecutive elements.  Every tile must lie within
+    // one segment.
+    int otile;
+    // generated input (first pass of a transform of the seeded uniform
+    // grid): the element at offset i of the grid is uniform_elem(gen_seed, i)
+    // instead of a load from `in`
+    int gen;
+    uint64_t gen_seed;
     int inv;            // 1: inverse (conjugate on load and on store)
     double scale;       // applied on store (1/N in the last inverse pass)
     // fused spectral evolution (contiguous passes only): element i of pencil
@@ -59,7 +71,9 @@ PassInfo find_pass(int esize, int n, bool contig, bool mx);
 // Strided complex64 pass that moves two adjacent pencils per 16-byte access
 // (needs an even number of pencils, pencil pairs adjacent in memory
 // (even `inner`) and 16-byte aligned buffers).  pencils_per_wg counts pencils.
-PassInfo find_pass_pair(int n);
+// `mx` selects the matrix-core radix-16 variant where one exists (the
+// returned mx field says which one it is).
+PassInfo find_pass_pair(int n, bool mx = false);
 
 // Twiddle tables of one axis: for each stage s with ns > 1, entry
 // off[s] + (q-1) ns + k = w_{ns r}^(q k), w_L = exp(-2 pi i / L), in binary64

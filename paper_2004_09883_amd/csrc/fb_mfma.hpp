@@ -87,12 +87,13 @@ __device__ __forceinline__ f32x4 mx_dot(const bf16x8 *w, bf16x8 xh, bf16x8 xl)
 
 // One radix-16 stage of a pass on the matrix cores.
 //
-// Wave w takes the four groups 4w .. 4w+3 of 16 butterflies; lane (c, g)
-// of group gamma works on butterfly beta = 16 gamma + c, whose pencil and
-// index b come from `map` (beta -> pp, b), and supplies its inputs
+// Wave w takes the G groups G w .. G w + G - 1 of 16 butterflies; lane
+// (c, g) of group gamma works on butterfly beta = 16 gamma + c, whose pencil
+// and index b come from `map` (beta -> pp, b), and supplies its inputs
 // q = 4g .. 4g+3 and receives its outputs k = 4g .. 4g+3.  The tile has
-// exactly P N / 16 threads, so the groups cover every butterfly once; waves
-// beyond the tile (`active` false, whole wavefronts) only take part in the
+// exactly P N / (4 G) threads (G = 4: one thread per butterfly; G = 8: tiles
+// of pencil pairs), so the groups cover every butterfly once; waves beyond
+// the tile (`active` false, whole wavefronts) only take part in the
 // barriers.
 //
 // Inputs come from `src` (element b + q N/16 of the pencil, twiddled here by
@@ -101,17 +102,17 @@ __device__ __forceinline__ f32x4 mx_dot(const bf16x8 *w, bf16x8 xh, bf16x8 xl)
 // either the LDS rows of the tile or the grid in global memory; when both
 // are LDS a barrier separates the reads from the writes, and when dst is LDS
 // a barrier ends the stage.
-template <int N, int Ns, int TWOFF, bool SRC_LDS, bool DST_LDS, class Map, class Src, class Dst>
+template <int N, int Ns, int TWOFF, bool SRC_LDS, bool DST_LDS, int G = 4, class Map, class Src, class Dst>
 __device__ __forceinline__ void mx_stage16(const float2 *__restrict__ tw, const MxConsts &A, int wave, int lane,
                                            bool active, const Map &map, const Src &src, const Dst &dst)
 {
     constexpr int NBF = N / 16;
     const int c = lane & 15, g = lane >> 4;
-    float2 x[4][4];
-    int ppv[4], bb[4];
+    float2 x[G][4];
+    int ppv[G], bb[G];
 #pragma unroll
-    for (int gi = 0; active && gi < 4; gi++) {
-        const int beta = 16 * (4 * wave + gi) + c;
+    for (int gi = 0; active && gi < G; gi++) {
+        const int beta = 16 * (G * wave + gi) + c;
         map(beta, ppv[gi], bb[gi]);
         const int b = bb[gi];
         const auto h = src.open(ppv[gi]);
@@ -127,7 +128,7 @@ __device__ __forceinline__ void mx_stage16(const float2 *__restrict__ tw, const 
     }
     if constexpr (SRC_LDS && DST_LDS) __syncthreads();
 #pragma unroll
-    for (int gi = 0; active && gi < 4; gi++) {
+    for (int gi = 0; active && gi < G; gi++) {
         bf16x8 xh, xl;
 #pragma unroll
         for (int i = 0; i < 4; i++) {
@@ -158,6 +159,17 @@ struct MxLds {
     __device__ __forceinline__ float2 *open(int pp) const { return lds + pp * LS; }
     __device__ __forceinline__ float2 load(float2 *row, int pos) const { return row[lds_pos(pos)]; }
     __device__ __forceinline__ void store(float2 *row, int pos, float2 v) const { row[lds_pos(pos)] = v; }
+};
+
+// LDS rows of a tile of pencil pairs: row j holds pencils 2j and 2j + 1
+// interleaved (element pos of pencil 2j + h at float2 index 2 lds_pos(pos) + h
+// of the row).
+struct MxLdsPair {
+    float2 *lds;
+    int LS;   // row stride in pairs
+    __device__ __forceinline__ float2 *open(int pp) const { return lds + (pp >> 1) * 2 * LS + (pp & 1); }
+    __device__ __forceinline__ float2 load(float2 *row, int pos) const { return row[2 * lds_pos(pos)]; }
+    __device__ __forceinline__ void store(float2 *row, int pos, float2 v) const { row[2 * lds_pos(pos)] = v; }
 };
 
 }  // namespace fb

@@ -154,26 +154,11 @@ hipError_t launch_checksum(int esize, const void *x, int64_t N, double *out2, hi
 
 // ---------------------------------------------------------------- inputs
 
-// SplitMix64 (Steele, Lea, Flood 2014) at counter c of stream `seed`:
-// the (c+1)-th output of the sequential generator started at state `seed`.
-__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c)
-{
-    uint64_t z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ double u_pm1(uint64_t h) { return (double)(h >> 11) * 0x1.0p-52 - 1.0; }
-
 template <typename V, typename R>
 __global__ void fill_uniform_kernel(V *x, int64_t N, uint64_t seed)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-        V v;
-        v.x = (R)u_pm1(splitmix64_at(seed, 2 * (uint64_t)i));
-        v.y = (R)u_pm1(splitmix64_at(seed, 2 * (uint64_t)i + 1));
-        x[i] = v;
+        x[i] = uniform_elem<V>(seed, (uint64_t)i);
     }
 }
 

@@ -48,13 +48,15 @@ template <typename V, int N, bool CONTIG> struct PassCfg {
 };
 
 // True when the matrix-core variant exists for this length and geometry:
-// complex64, a radix-16 stage, 16 elements per thread and whole wavefronts.
+// complex64 (single pencils, or pencil pairs in a strided pass), a radix-16
+// stage, 16 elements per thread and whole wavefronts.
 template <typename V, int N, bool CONTIG> constexpr bool mx_capable()
 {
     using Cfg = PassCfg<V, N, CONTIG>;
     bool has16 = false;
     for (int s = 0; s < Cfg::RP.count; s++) has16 = has16 || Cfg::RP.r[s] == 16;
-    return sizeof(V) == 8 && has16 && N % 16 == 0 && Cfg::THREADS % 64 == 0;
+    const bool c64 = std::is_same<V, float2>::value || (std::is_same<V, c2x>::value && !CONTIG);
+    return c64 && has16 && N % 16 == 0 && Cfg::THREADS % 64 == 0;
 }
 
 // Streaming global access: the grid is read once and written once per pass,
@@ -114,18 +116,30 @@ template <typename V> __device__ __forceinline__ void st_v(elem_t<V> *p, V v)
     }
 }
 
-// Pre-twiddle of element e of local pencil lp (and lp + 1 for a pair).
-template <typename V> __device__ __forceinline__ V pre_twiddle(V v, int64_t e, int64_t lp, const void *ptw, int64_t L)
+// Pre-twiddle of element e of local pencil lp (and lp + 1 for a pair):
+// the factor is ptw[e lp].  The product stays below the table length without
+// a reduction because e < N and lp < seg_pencils, and the table holds
+// N seg_pencils roots (checked on the host), so 32-bit arithmetic suffices.
+template <typename V> __device__ __forceinline__ V pre_twiddle(V v, int e, int lp, const void *ptw)
 {
     const tw_t<V> *t = (const tw_t<V> *)ptw;
+    const unsigned i = (unsigned)e * (unsigned)lp;
     if constexpr (std::is_same<V, c2x>::value) {
-        v.a = cmul(v.a, t[(e * lp) % L]);
-        v.b = cmul(v.b, t[(e * (lp + 1)) % L]);
+        v.a = cmul(v.a, t[i]);
+        v.b = cmul(v.b, t[i + (unsigned)e]);
         return v;
     } else {
-        return cmul(v, t[(e * lp) % L]);
+        return cmul(v, t[i]);
     }
 }
+
+// Whether the first / last matrix-core stage may read / write global memory
+// directly (1) or always go through LDS (0).  Direct access saves two LDS
+// round trips per pass but measured slower on MI355X (512x256x256 forward +
+// inverse: 405 us direct, 318 us through LDS), so it is off by default.
+#ifndef FB_MX_DIRECT
+#define FB_MX_DIRECT 0
+#endif
 
 template <typename V, int N, bool CONTIG, bool MX> struct MxStage {
     // whether stage s runs on the matrix cores
@@ -134,7 +148,10 @@ template <typename V, int N, bool CONTIG, bool MX> struct MxStage {
     // itself: contiguous passes always (16 consecutive butterflies of one
     // pencil are 16 consecutive elements), strided passes when 16 adjacent
     // pencils fit in the tile (they are 16 consecutive elements)
-    static constexpr bool direct() { return MX && (CONTIG || PassCfg<V, N, CONTIG>::P % 16 == 0); }
+    static constexpr bool direct()
+    {
+        return FB_MX_DIRECT && MX && std::is_same<V, float2>::value && (CONTIG || PassCfg<V, N, CONTIG>::P % 16 == 0);
+    }
 };
 
 // Butterfly numbering of the matrix-core stages: beta -> (pencil, b).
@@ -188,7 +205,9 @@ struct MxGlobalIn {
     __device__ __forceinline__ float2 load(const H &h, int pos) const
     {
         if (!h.ok) return make_float2(0.f, 0.f);
-        float2 v = ld_stream(h.p + (int64_t)pos * a->stride);
+        float2 v = a->gen ? uniform_elem<float2>(a->gen_seed, (uint64_t)(h.p - (const float2 *)a->in) +
+                                                                   (uint64_t)pos * (uint64_t)a->stride)
+                          : ld_stream(h.p + (int64_t)pos * a->stride);
         if (a->evolve) v = cscale(v, h.g * gtab[pos]);
         if (a->inv) v = cconj(v);
         return v;
@@ -229,6 +248,65 @@ struct MxGlobalOut {
     }
 };
 
+// Tile-contiguous output of a strided vector-unit pass (PassArgs::otile):
+// the last stage's outputs go to LDS in natural order, then the workgroup
+// writes the tile's block of P x N elements with consecutive threads on
+// consecutive elements.  On entry the LDS rows are free (the last stage has
+// read its inputs and passed a barrier).
+template <typename V, int N, bool CONTIG, int M>
+__device__ __forceinline__ void store_tile_contiguous(const PassArgs &a, int64_t tile, int tid, bool active,
+                                                      bool valid, int t, V *row, V *lds, const V (&v)[M])
+{
+    using Cfg = PassCfg<V, N, CONTIG>;
+    using R = real_t<V>;
+    constexpr RadixPlan RP = Cfg::RP;
+    constexpr int T = Cfg::T, P = Cfg::P, LS = Cfg::LS;
+    constexpr int RL = RP.r[RP.count - 1];
+    constexpr int NBF = N / RL;
+    constexpr int U = (NBF + T - 1) / T;
+    constexpr bool PAIR = std::is_same<V, c2x>::value;
+    constexpr int UNIT = PAIR ? 2 : 1;
+    if (valid) {
+        const R sc = (R)a.scale;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int b = t + T * u;
+            if (NBF % T == 0 || b < NBF) {
+#pragma unroll
+                for (int q = 0; q < RL; q++) {
+                    V o = v[u * RL + q];
+                    if (a.inv) o = cconj(o);
+                    if (a.scale != 1.0) o = cscale(o, sc);
+                    row[lds_pos(b + q * NBF)] = o;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int64_t p0 = tile * P * UNIT;   // first pencil of the tile
+    if (active && p0 < a.npencils) {
+        int64_t seg0 = 0, lp0 = p0;
+        if (a.seg_off) {
+            seg0 = a.seg_off[p0 / a.seg_pencils];
+            lp0 = p0 % a.seg_pencils;
+        }
+        const int64_t ob = seg0 + (a.ostride ? (lp0 / a.oinner) * a.oouter + (lp0 % a.oinner) * a.oistep
+                                             : (lp0 / a.inner) * a.outer + (lp0 % a.inner) * a.istep);
+        const int64_t np = a.npencils - p0 < P * UNIT ? a.npencils - p0 : P * UNIT;
+        const int count = (int)np * N;
+        elem_t<V> *o = (elem_t<V> *)a.out + ob;
+        for (int i = tid; i < count; i += Cfg::THREADS) {
+            const int j = i / N, k = i - (i / N) * N;
+            if constexpr (PAIR) {
+                const c2x &e = lds[(j >> 1) * LS + lds_pos(k)];
+                st_stream(o + i, (j & 1) ? e.b : e.a);
+            } else {
+                st_stream(o + i, lds[j * LS + lds_pos(k)]);
+            }
+        }
+    }
+}
+
 #ifdef FB_WAVES_PER_EU
 #define FB_OCCUPANCY __attribute__((amdgpu_waves_per_eu(FB_WAVES_PER_EU)))
 #else
@@ -249,7 +327,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
     constexpr int NST = RP.count;
     static_assert(!MX || mx_capable<V, N, CONTIG>(), "no matrix-core variant for this pass");
     constexpr bool PAIR = std::is_same<V, c2x>::value;   // each unit is two adjacent pencils
-    static_assert(!PAIR || (!CONTIG && !MX), "pencil pairs are for strided vector-unit passes");
+    static_assert(!PAIR || !CONTIG, "pencil pairs are for strided passes");
     using E = elem_t<V>;
     using TW = tw_t<V>;
 
@@ -306,8 +384,14 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
             for (int u = 0; u < U; u++) {
                 const int b = t + T * u;
                 if (NBF % T == 0 || b < NBF) {
+                    if (a.gen) {
 #pragma unroll
-                    for (int q = 0; q < R0; q++) v[u * R0 + q] = ld_v<V>(gin + (int64_t)(b + q * NBF) * S);
+                        for (int q = 0; q < R0; q++)
+                            v[u * R0 + q] = uniform_elem<V>(a.gen_seed, (uint64_t)(base + (int64_t)(b + q * NBF) * S));
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < R0; q++) v[u * R0 + q] = ld_v<V>(gin + (int64_t)(b + q * NBF) * S);
+                    }
                 }
             }
             if constexpr (CONTIG) {
@@ -334,8 +418,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                     if (NBF % T == 0 || b < NBF) {
 #pragma unroll
                         for (int q = 0; q < R0; q++) {
-                            const int64_t e = b + q * NBF;
-                            if (e > 0) v[u * R0 + q] = pre_twiddle(v[u * R0 + q], e, lp, a.ptw, a.ptw_len);
+                            const int e = b + q * NBF;
+                            if (e > 0) v[u * R0 + q] = pre_twiddle(v[u * R0 + q], e, (int)lp, a.ptw);
                         }
                     }
                 }
@@ -407,6 +491,12 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                 // the 16 lanes of a group touch 16 adjacent pencils (consecutive addresses)
                 if constexpr (!CONTIG && MXS::direct()) run(MxMapStrided<P>{});
                 else run(MxMapContig<N / 16>{});
+            } else if constexpr (PAIR) {
+                // a tile of P pencil pairs is 2P pencils of complex64 for the matrix
+                // cores: each wave takes twice the butterfly groups
+                const MxLdsPair ldsp{(float2 *)lds, LS};
+                mx_stage16<N, Ns, RP.twoff[s], true, true, 8>((const float2 *)tw, mxc, tid >> 6, tid & 63, active,
+                                                              MxMapContig<N / 16>{}, ldsp, ldsp);
             }
         } else {
             if constexpr (s > 0) {
@@ -469,6 +559,12 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
 #pragma unroll
                     for (int q = 0; q < RL; q++) v[u * RL + q] = row[lds_pos(b + q * NBF)];
                 }
+            }
+        }
+        if constexpr (!CONTIG && !MX) {
+            if (a.otile) {   // uniform over the workgroup
+                store_tile_contiguous<V, N, CONTIG>(a, tile, tid, active, valid, t, row, lds, v);
+                return;
             }
         }
         if (valid && !MX_OUT) {

@@ -3,5 +3,5 @@
 #include "fb_pass_inst.hpp"
 
 namespace fb {
-PassInfo find_pass_pair(int n) { return find_pass_pair_t(n); }
+PassInfo find_pass_pair(int n, bool mx) { return find_pass_pair_t(n, mx); }
 }  // namespace fb

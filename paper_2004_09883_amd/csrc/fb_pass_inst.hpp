@@ -37,17 +37,21 @@ template <typename V, int N> PassInfo pass_info(bool contig, bool mx)
     X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) \
     X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096)
 
-// Strided complex64 passes over pencil pairs (16-byte accesses).
-template <int N> PassInfo pass_info_pair()
+// Strided complex64 passes over pencil pairs (16-byte accesses); MX selects
+// the matrix-core radix-16 variant where one exists.
+template <int N> PassInfo pass_info_pair(bool mx)
 {
     using Cfg = PassCfg<c2x, N, false>;
+    if constexpr (mx_capable<c2x, N, false>()) {
+        if (mx) return {&launch_pass<c2x, N, false, true>, 2 * Cfg::P, Cfg::THREADS, 1};
+    }
     return {&launch_pass<c2x, N, false, false>, 2 * Cfg::P, Cfg::THREADS, 0};
 }
 
-inline PassInfo find_pass_pair_t(int n)
+inline PassInfo find_pass_pair_t(int n, bool mx)
 {
     switch (n) {
-#define FB_CASE(L) case L: return pass_info_pair<L>();
+#define FB_CASE(L) case L: return pass_info_pair<L>(mx);
         FB_FOR_EACH_LENGTH(FB_CASE)
 #undef FB_CASE
     default: return {nullptr, 0, 0, 0};

@@ -209,8 +209,7 @@ int launch(fb_server *s, Slot &sl)
     if (e == hipSuccess && r.want_grid) e = hipHostMalloc(&sl.grid_host, sl.grid_bytes, hipHostMallocDefault);
     if (e != hipSuccess) return FB_ERR_OOM;
     const uint64_t seed = splitmix64_at(r.seed, (uint64_t)r.request_key);
-    int rc = fb_fill_uniform(p, sl.u0, seed, sl.stream);
-    if (!rc) rc = fb_fft3d_exec(p, sl.u0, sl.u0, FB_FORWARD, sl.stream);
+    int rc = fb_fft3d_forward_uniform(p, seed, sl.u0, sl.stream);
     for (int t = 1; !rc && t <= r.steps; t++)
         rc = fb_spectral_step(p, sl.u0, sl.x, r.alpha, (double)t, sl.sums_dev + 2 * (t - 1), sl.stream);
     if (rc) return rc;

@@ -20,12 +20,13 @@ HBM_PEAK_GBS = 8000.0
 
 
 def request_model_bytes(shape, is_c64: bool, steps: int) -> float:
-    """Bytes a request moves under the pencil-pass model: input generation
-    writes the grid once, every 3D transform reads and writes it once per
-    pass (3 passes), the evolution is fused into the first inverse pass."""
+    """Bytes a request moves under the pencil-pass model: every 3D transform
+    reads and writes the grid once per pass (3 passes); the input is
+    generated inside the first forward pass (it writes only), the evolution
+    is fused into the first inverse pass."""
     n = math.prod(shape)
     e = 8 if is_c64 else 16
-    return e * n + (1 + steps) * 3 * 2 * e * n
+    return (1 + steps) * 3 * 2 * e * n - e * n
 
 
 def request_flops(shape, steps: int) -> float:
@@ -96,6 +97,10 @@ def run_serving(rate: float = 2000.0, duration: float = 10.0, warmup: float = 1.
         "model_gbs": round(model_bytes / span / 1e9, 1),
         "gflops": round(flops / span / 1e9, 1),
         "offered_load_rho": round(offered_bps / (HBM_PEAK_GBS * 1e9), 3),
+        "offered_model_gbs": round(offered_bps / 1e9, 1),
+        # served slower than requests arrived: the queue grows for the whole
+        # run and the latency percentiles grow with its duration
+        "saturated": bool(len(measured) / span < 0.97 * rate),
         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
         "mean_ms": round(float(lat.mean()) * 1e3, 3),
