@@ -33,7 +33,8 @@ ALPHA = 1e-6
 T_STEPS = 20
 SEED = 1
 KERNEL_SOURCES = ["paper_2004_09883_amd/csrc/fb_pass.hpp", "paper_2004_09883_amd/csrc/fb_device.hpp",
-                  "paper_2004_09883_amd/csrc/fb_plan_rules.hpp", "paper_2004_09883_amd/csrc/fb_pass_inst.hpp"]
+                  "paper_2004_09883_amd/csrc/fb_plan_rules.hpp", "paper_2004_09883_amd/csrc/fb_pass_inst.hpp",
+                  "paper_2004_09883_amd/csrc/fb_mfma.hpp", "paper_2004_09883_amd/csrc/fb_internal.hpp"]
 
 
 def flops_fft(shape) -> float:
@@ -64,6 +65,62 @@ def traffic_for(kernel: str):
     return None if rec is None else rec.get("hbm_bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def small_block_section(torch, fb, reps: int = 20) -> dict:
+    """The 64^3 complex128 block (seed 1, alpha = 1e-6, 6 steps): too small
+    for the bandwidth roofline (launch and latency bound), so its latency is
+    reported: forward + 6 fused steps, eager launches and one graph replay."""
+    shape, steps = (64, 64, 64), 6
+    plan = fb.Plan(*shape, fb.FB_C128)
+    x0 = torch.empty(shape, dtype=torch.complex128, device="cuda")
+    u0 = torch.empty_like(x0)
+    xt = torch.empty_like(x0)
+    sums = torch.zeros((steps, 2), dtype=torch.float64, device="cuda")
+    fb.fb_fill_uniform(plan, x0, 1)
+
+    def block():
+        fb.fb_fft3d_exec(plan, x0, u0, fb.FB_FORWARD)
+        for t in range(1, steps + 1):
+            fb.fb_spectral_step(plan, u0, xt, ALPHA, float(t), sums[t - 1])
+
+    for _ in range(5):
+        block()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        block()
+    e.record()
+    torch.cuda.synchronize()
+    eager = s.elapsed_time(e) / reps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        block()
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        g.replay()
+    e.record()
+    torch.cuda.synchronize()
+    replay = s.elapsed_time(e) / reps
+    del g
+    return {"workload": "64x64x64 complex128, forward 3D FFT + 6 x (evolve alpha=1e-6 + inverse + checksum)",
+            "block_ms_eager": round(eager, 4), "block_ms_graph": round(replay, 4),
+            "launches": 3 + steps * 4}
+
+
 def cpu_baseline(budget_steps: int = 10) -> dict:
     """The oracle (plain C, binary64) on the host cores: forward 3D FFT plus
     `budget_steps` of the 20 evolve/inverse/checksum steps of the same
@@ -80,13 +137,22 @@ def cpu_baseline(budget_steps: int = 10) -> dict:
         xt = oracle.fft3d(oracle.evolve(X0, ALPHA, t), +1)
         oracle.checksum(xt)
     dt = time.perf_counter() - t0
-    return {"value": round((1 + budget_steps) * flops_fft(SHAPE) / dt / 1e9, 3), "unit": "GFLOP/s",
-            "cores": oracle.threads(), "kind": "oracle",
+    # the same oracle on one core: one forward transform
+    nthreads = oracle.threads()
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.fft3d(x0, -1)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(nthreads)
+    return {"value": round((1 + budget_steps) * flops_fft(SHAPE) / dt / 1e9, 3),
+            "value_1_thread": round(flops_fft(SHAPE) / dt1 / 1e9, 3), "unit": "GFLOP/s",
+            "cores": oracle.threads(), "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"forward FFT + {budget_steps} of the {T_STEPS} evolve/inverse/checksum steps of the "
-                      f"{SHAPE[0]}x{SHAPE[1]}x{SHAPE[2]} complex128 block ({dt:.2f} s wall)"}
+                      f"{SHAPE[0]}x{SHAPE[1]}x{SHAPE[2]} complex128 block ({dt:.2f} s wall); one-thread value: one "
+                      f"forward FFT ({dt1:.2f} s)"}
 
 
-def forms_section(torch, fb, reps: int = 20, steps: int = 10) -> dict:
+def forms_section(torch, fb, reps: int = 50, steps: int = 10) -> dict:
     """512 x 256 x 256 grid of N(0,1) entries (Box-Muller, seed 2; the
     complex64 forms get the values rounded to complex64): per form the
     forward 3D FFT and one fused spectral step (evolve + inverse FFT +
@@ -112,7 +178,9 @@ def forms_section(torch, fb, reps: int = 20, steps: int = 10) -> dict:
         u = torch.empty_like(x)
         xt = torch.empty_like(x)
         sums = torch.zeros(2, dtype=torch.float64, device="cuda")
-        for _ in range(3):
+        # warm-up long enough (~100 transforms) for the clocks to settle
+        # after the host-to-device copy of the input
+        for _ in range(100):
             fb.fb_fft3d_exec(plan, x, u, fb.FB_FORWARD)
         torch.cuda.synchronize()
         s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -122,6 +190,17 @@ def forms_section(torch, fb, reps: int = 20, steps: int = 10) -> dict:
         e.record()
         torch.cuda.synchronize()
         ms = s.elapsed_time(e) / reps
+        # the same forward in place (w -> w, on a copy so that u stays the
+        # spectrum of x): one grid instead of two, so more of it stays in the
+        # 256 MB last-level cache for the complex64 forms
+        w = u.clone()
+        s.record()
+        for _ in range(reps):
+            fb.fb_fft3d_exec(plan, w, w, fb.FB_FORWARD)
+        e.record()
+        torch.cuda.synchronize()
+        ms_in_place = s.elapsed_time(e) / reps
+        del w
         s.record()
         for _ in range(reps):
             fb.fb_spectral_step(plan, u, xt, ALPHA, float(steps), sums)
@@ -138,7 +217,8 @@ def forms_section(torch, fb, reps: int = 20, steps: int = 10) -> dict:
                   for k in fb.fb_profile_report()]
         fb.fb_profile_enable(False)
         b_alg = 3 * 2 * esize * n
-        rec = {"forward_ms": round(ms, 4), "gflops": round(flops_fft(shape) / ms / 1e6, 1),
+        rec = {"forward_ms": round(ms, 4), "forward_in_place_ms": round(ms_in_place, 4),
+               "gflops": round(flops_fft(shape) / ms / 1e6, 1),
                "hbm_roofline_frac": round(b_alg / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
                "step_ms": round(ms_step, 4),
                "step_hbm_roofline_frac": round(b_alg / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
@@ -154,6 +234,9 @@ def forms_section(torch, fb, reps: int = 20, steps: int = 10) -> dict:
         torch.cuda.empty_cache()
     out["c64_speedup_vs_c128"] = round(out["c128"]["forward_ms"] / out["c64"]["forward_ms"], 3)
     out["c64_splitbf16_speedup_vs_c128"] = round(out["c128"]["forward_ms"] / out["c64_splitbf16"]["forward_ms"], 3)
+    for k in ("c64", "c64_splitbf16"):
+        out[k + "_in_place_speedup_vs_c128"] = round(out["c128"]["forward_in_place_ms"] / out[k]["forward_in_place_ms"],
+                                                     3)
     out["workload"] = ("512x256x256 grid, N(0,1) entries (Box-Muller, seed 2): forward 3D FFT (3 pencil passes) "
                        "and one spectral step at t=%d, alpha=1e-6" % steps)
     del ref
@@ -280,6 +363,13 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate of the serving run")
     ap.add_argument("--serve-sweep", type=float, default=3.0,
                     help="seconds per rate of the 500/1000/1500 req/s context sweep (0: skip)")
+    ap.add_argument("--forms-only", action="store_true",
+                    help="only run the 512x256x256 precision-form section (for counter runs)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the cache-flushed and fused-steps timings of the block (profiling runs: only the "
+                         "timed block's kernels are launched)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the batched-form section (for kernel traces)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain 512 MiB copy (counter calibration)")
     args = ap.parse_args()
@@ -299,6 +389,12 @@ def main() -> int:
     fb.load()
     if args.copy_only:
         print(json.dumps({"copy_reference": copy_reference(torch)}), flush=True)
+        return 0
+    if args.forms_only:
+        print(json.dumps({"forms_512x256x256": forms_section(torch, fb, reps=10)}), flush=True)
+        return 0
+    if args.batched_only:
+        print(json.dumps({"batched": batched_section(torch, fb)}), flush=True)
         return 0
 
     plan = fb.Plan(*SHAPE, fb.FB_C128)
@@ -352,19 +448,47 @@ def main() -> int:
 
     ms = start.elapsed_time(stop) / args.steps
 
-    # the same block started cold: a 512 MiB write before each block evicts
-    # the grids from the 256 MB last-level cache (the write is not timed)
-    flush = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")
-    cold = 0.0
-    for _ in range(args.steps):
-        flush.fill_(1)
+    cold_ms = fused_ms = None
+    if not args.no_extras:
+        # the same block started cold: a 512 MiB write before each block
+        # evicts the grids from the 256 MB last-level cache (not timed)
+        flush = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")
+        cold = 0.0
+        for _ in range(args.steps):
+            flush.fill_(1)
+            start.record()
+            run()
+            stop.record()
+            torch.cuda.synchronize()
+            cold += start.elapsed_time(stop)
+        cold_ms = cold / args.steps
+        del flush
+
+    if not args.no_extras:
+        # the same block with the steps computed by fb_spectral_steps: chunks
+        # of up to 8 steps share their first inverse pass (one read of the
+        # spectrum), at the price of 20 output grids instead of one
+        xs = torch.empty((T_STEPS,) + SHAPE, dtype=torch.complex128, device="cuda")
+        sums_m = torch.zeros_like(sums)
+        ts = [float(t) for t in range(1, T_STEPS + 1)]
+
+        def step_fused():
+            fb.fb_fft3d_exec(plan, x0, u0, fb.FB_FORWARD)
+            fb.fb_spectral_steps(plan, u0, xs, ALPHA, ts, sums_m)
+
+        for _ in range(args.warmup):
+            step_fused()
+        torch.cuda.synchronize()
         start.record()
-        run()
+        for _ in range(args.steps):
+            step_fused()
         stop.record()
         torch.cuda.synchronize()
-        cold += start.elapsed_time(stop)
-    cold_ms = cold / args.steps
-    del flush
+        fused_ms = start.elapsed_time(stop) / args.steps
+        if not torch.equal(sums_m, sums):
+            print("fb_spectral_steps checksums differ from fb_spectral_step", file=sys.stderr)
+            return 1
+        del xs
 
     flops_step = (1 + T_STEPS) * flops_fft(SHAPE)
     value = flops_step / (ms * 1e-3) / 1e9
@@ -389,10 +513,14 @@ def main() -> int:
                       "transforms_per_step": 1 + T_STEPS, "wall_s": round(wall, 3),
                       "launch": "hip graph (one replay per step)" if graph is not None else "eager",
                       "eager_ms_per_step": round(eager_ms, 4),
-                      "cache_flushed_ms_per_step": round(cold_ms, 4)},
+                      "cache_flushed_ms_per_step": None if cold_ms is None else round(cold_ms, 4),
+                      "fused_steps_ms_per_step": None if fused_ms is None else round(fused_ms, 4)},
            "roofline": roofline,
            "kernels": [{k: v for k, v in p.items()} for p in prof]}
     if not args.no_forms:
+        rec["block_64x64x64"] = small_block_section(torch, fb)
+        from paper_2004_09883_amd import offload
+        rec["offload_search_64x64x64"] = offload.search(torch, fb, shape=(64, 64, 64), alpha=ALPHA, steps=6)
         rec["forms_512x256x256"] = forms_section(torch, fb)
         rec["batched"] = batched_section(torch, fb)
         rec["paper_2d_2048"] = paper_2d_section(torch, fb)

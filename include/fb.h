@@ -128,6 +128,18 @@ fb_status fb_checksum(const fb_plan *p, const void *x, double *out2_dev, void *h
 fb_status fb_spectral_step(const fb_plan *p, const void *uhat0, void *x_out, double alpha,
                            double t, double *out2_dev, void *hip_stream);
 
+/* Several steps of the spectral block from one spectrum: for j < nsteps,
+ * grid j of x_out (x_out + j N elements) = inverse(evolve(uhat0, alpha,
+ * t[j])), and its checksum into sums_dev[2j], sums_dev[2j+1] (when sums_dev
+ * is not NULL).  Each grid equals what fb_spectral_step gives for t[j], bit
+ * for bit; the steps share the first inverse pass, which reads uhat0 once for
+ * up to 8 steps and writes their grids, so a step moves 5 grid sweeps
+ * instead of 6 (the paper's block is one library call of the same meaning,
+ * section 3.4 B-1).  t is a host array of nsteps finite values >= 0; x_out
+ * holds nsteps grids and must not overlap uhat0. */
+fb_status fb_spectral_steps(const fb_plan *p, const void *uhat0, void *x_out, double alpha, const double *t,
+                            int nsteps, double *sums_dev, void *hip_stream);
+
 /* Fill a grid of the plan's shape and dtype with the seeded uniform input:
  * element i = U(seed, 2i) + i U(seed, 2i+1), U(s, c) = (h >> 11) 2^-52 - 1
  * with h the SplitMix64 output at counter c of stream s (complex64 grids get
@@ -183,15 +195,15 @@ fb_status fb_batch_exec(const fb_batch *b, const void *in, void *out, void *work
 /* ---- Serving form ------------------------------------------------------
  * A request loop with continuous batching: submitted spectral-block
  * requests wait in a FIFO; a worker thread admits the head as soon as a
- * stream slot is free and the request's device bytes (two grids and its
- * checksums) fit in the HBM budget, so work of requests that arrive while
- * others run overlaps on the device.  Plans (per shape and dtype) and device
+ * stream slot is free and the request's device bytes (the spectrum,
+ * min(steps, 8) output grids and its checksums) fit in the HBM budget, so
+ * work of requests that arrive while others run overlaps on the device.  Plans (per shape and dtype) and device
  * buffers (per size) stay resident; pooled buffers count against the budget.
  * A request: its input grid (as fb_fill_uniform with the stream seed
  * SplitMix64(seed, request_key)) is generated inside the first forward
  * pass (fb_fft3d_forward_uniform) and transformed forward,
  * then for t = 1..steps evolved (alpha, t), transformed back and
- * checksummed; the checksums (and the final grid when want_grid) come back
+ * checksummed, up to 8 steps per read of the spectrum (fb_spectral_steps); the checksums (and the final grid when want_grid) come back
  * to host memory.  A result does not depend on what else runs. */
 #define FB_SERVE_MAX_STEPS 64
 

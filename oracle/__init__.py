@@ -40,6 +40,7 @@ def _load():
     lib = ctypes.CDLL(_LIB)
     i64, dp, i32 = ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_int
     lib.orc_threads.restype = i32
+    lib.orc_set_threads.argtypes = [i32]
     lib.orc_radices.argtypes = [i64, ctypes.POINTER(i32), i32]
     lib.orc_describe.argtypes = [i64, i64, i64, ctypes.c_char_p, i32]
     lib.orc_omega.argtypes = [i64, i64, i32, dp, dp]
@@ -69,6 +70,11 @@ def _as_grid(x) -> np.ndarray:
 
 def threads() -> int:
     return int(_load().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads used by later calls (timing only; results do not depend on it)."""
+    _load().orc_set_threads(int(n))
 
 
 def radices(n: int) -> list[int]:

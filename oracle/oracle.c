@@ -75,6 +75,18 @@ int orc_threads(void)
 #endif
 }
 
+/* Thread count of later calls (for timing the oracle on one core); no
+ * effect on results: every pencil is computed by one thread in a fixed
+ * order whatever the count. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Radix list of n (see the header); returns the count, or -1 when n is not
  * of the form 2^a 3^b with n >= 1.  n == 1 has an empty list. */
 int orc_radices(int64_t n, int *out, int cap)

@@ -233,32 +233,56 @@ const void *axis_table(const fb_plan *p, int a)
     return p->tw32 + p->ax[a].tw_off;
 }
 
-// Largest element index touched by a pass; must stay below N.
-bool pass_in_bounds(const fb_plan *p, const AxisPlan &A)
+// Largest element index touched by a pass over `total` elements; must stay
+// below it.
+bool pass_in_bounds(const PassArgs &g, int64_t n, int64_t total)
 {
-    const int64_t np = A.npencils;
-    const int64_t in_max = (np < A.inner ? np : A.inner) - 1;
-    const int64_t max_base = ((np - 1) / A.inner) * A.outer + in_max * A.istep;
-    return max_base + (A.n - 1) * A.stride < p->N && max_base >= 0;
+    const int64_t np = g.npencils;
+    const int64_t in_max = (np < g.inner ? np : g.inner) - 1;
+    const int64_t max_base = ((np - 1) / g.inner) * g.outer + in_max * g.istep;
+    return max_base + (n - 1) * g.stride < total && max_base >= 0;
 }
 
+// Evolution constants of a multi-output evolve pass.
+struct MultiOut {
+    int nout;
+    double cs[FB_MAX_FUSED_STEPS];
+};
+
+// One pencil pass along axis a.  ngrids > 1 runs it over that many
+// consecutive grids in one launch; `multi` (contiguous evolve pass only)
+// writes multi->nout outputs, N elements apart, from one read of `in`.
 int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, double scale, const PassArgs *ev,
-                hipStream_t st, const uint64_t *gen_seed = nullptr)
+                hipStream_t st, const uint64_t *gen_seed = nullptr, int ngrids = 1, const MultiOut *multi = nullptr)
 {
     const AxisPlan &A = p->ax[a];
     if (!A.pass.launch) return fail(FB_ERR_UNSUPPORTED_SIZE, "no pass for length %lld", (long long)A.n);
-    const bool pair = A.pass_pair.launch && (uintptr_t)in % 16 == 0 && (uintptr_t)out % 16 == 0;
-    const PassInfo &pi = pair ? A.pass_pair : A.pass;
-    if (!pass_in_bounds(p, A)) return fail(FB_ERR_INVALID_ARG, "internal: pass geometry out of bounds");
+    const bool pair = !multi && A.pass_pair.launch && (uintptr_t)in % 16 == 0 && (uintptr_t)out % 16 == 0;
+    PassInfo pm{nullptr, 0, 0, 0};
+    if (multi) {
+        if (!A.contig || !ev || ngrids != 1 || multi->nout < 1 || multi->nout > FB_MAX_FUSED_STEPS)
+            return fail(FB_ERR_INVALID_ARG, "internal: multi-output pass misuse");
+        pm = fb::find_pass_multi(p->esize, (int)A.n, A.pass.mx != 0);
+        if (!pm.launch || pm.mx != A.pass.mx) return fail(FB_ERR_UNSUPPORTED_SIZE, "no multi-output pass");
+    }
+    const PassInfo &pi = multi ? pm : pair ? A.pass_pair : A.pass;
     PassArgs args{};
     args.in = in;
     args.out = out;
     args.tw = axis_table(p, a);
-    args.npencils = A.npencils;
+    args.npencils = A.npencils * ngrids;
     args.inner = A.inner;
-    args.outer = A.outer;
+    // the x axis has all pencils of a grid in its inner group; further grids
+    // follow N elements apart
+    args.outer = (ngrids > 1 && A.npencils <= A.inner) ? p->N : A.outer;
     args.istep = A.istep;
     args.stride = A.stride;
+    if (!pass_in_bounds(args, A.n, p->N * ngrids)) return fail(FB_ERR_INVALID_ARG, "internal: pass geometry out of bounds");
+    if (multi) {
+        args.nout = multi->nout;
+        args.out_step = p->N;
+        for (int j = 0; j < multi->nout; j++) args.ev_cs[j] = multi->cs[j];
+    }
     args.inv = inv;
     args.scale = scale;
     if (ev) {
@@ -272,12 +296,19 @@ int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, dou
         args.gen = 1;
         args.gen_seed = *gen_seed;
     }
-    char name[96];
-    snprintf(name, sizeof name, "fft_pass<%s,n=%lld,%s%s%s%s%s>", dtype_tag(p->esize), (long long)A.n,
+    char name[128];
+    char multi_tag[32] = "";
+    if (multi) snprintf(multi_tag, sizeof multi_tag, ",outputs=%d", multi->nout);
+    char grids_tag[32] = "";
+    if (ngrids > 1) snprintf(grids_tag, sizeof grids_tag, ",grids=%d", ngrids);
+    snprintf(name, sizeof name, "fft_pass<%s,n=%lld,%s%s%s%s%s%s%s>", dtype_tag(p->esize), (long long)A.n,
              A.contig ? "contiguous" : "strided", pi.mx ? ",mfma" : "", pair ? ",pairs" : "", ev ? ",evolve" : "",
-             gen_seed ? ",generated-input" : "");
-    // a pass with generated input only writes the grid
-    const double bytes = (gen_seed ? 1.0 : 2.0) * (double)p->N * (double)p->esize;
+             gen_seed ? ",generated-input" : "", multi_tag, grids_tag);
+    // a pass with generated input only writes the grid; a multi-output pass
+    // reads once and writes nout times
+    const double reads = gen_seed ? 0.0 : 1.0;
+    const double writes = multi ? (double)multi->nout : 1.0;
+    const double bytes = (reads + writes) * (double)ngrids * (double)p->N * (double)p->esize;
     hipError_t e = timed_launch(name, bytes, st, [&] { return pi.launch(args, st); });
     if (e != hipSuccess) return hip_fail(e, "pass launch");
     return FB_OK;
@@ -565,6 +596,63 @@ fb_status fb_spectral_step(const fb_plan *p, const void *uhat0, void *x_out, dou
         hipError_t e = timed_launch(p->esize == 16 ? "checksum<c128>" : "checksum<c64>", 1024.0 * p->esize + 16, st,
                                     [&] { return fb::launch_checksum(p->esize, x_out, p->N, out2_dev, st); });
         if (e != hipSuccess) return (fb_status)hip_fail(e, "checksum launch");
+    }
+    return (fb_status)ok();
+}
+
+fb_status fb_spectral_steps(const fb_plan *p, const void *uhat0, void *x_out, double alpha, const double *t,
+                            int nsteps, double *sums_dev, void *hip_stream)
+{
+    if (check_plan(p) || check_grid_ptr(p, uhat0, "uhat0") || check_grid_ptr(p, x_out, "x_out"))
+        return (fb_status)g_code;
+    if (nsteps < 1 || !t) return (fb_status)fail(FB_ERR_INVALID_ARG, "need nsteps >= 1 and a host array t");
+    for (int j = 0; j < nsteps; j++)
+        if (check_alpha_t(alpha, t[j])) return (fb_status)g_code;
+    if (sums_dev && (uintptr_t)sums_dev % 8) return (fb_status)fail(FB_ERR_INVALID_ARG, "sums_dev is misaligned");
+    {
+        const uintptr_t u = (uintptr_t)uhat0, x = (uintptr_t)x_out;
+        const uintptr_t g = (uintptr_t)(p->N * p->esize), xs = g * (uintptr_t)nsteps;
+        if (u < x + xs && x < u + g) return (fb_status)fail(FB_ERR_INVALID_ARG, "fb_spectral_steps: x_out overlaps uhat0");
+    }
+    if (check_device(p)) return (fb_status)g_code;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t gbytes = (size_t)p->N * (size_t)p->esize;
+    if (p->nz <= 1) {   // no contiguous evolve pass to share: one step at a time
+        for (int j = 0; j < nsteps; j++) {
+            fb_status rc = fb_spectral_step(p, uhat0, (char *)x_out + gbytes * j, alpha, t[j],
+                                            sums_dev ? sums_dev + 2 * j : nullptr, hip_stream);
+            if (rc) return rc;
+        }
+        return (fb_status)ok();
+    }
+    int last = -1;
+    double nsel = 1.0;
+    for (int a = 0; a < 3; a++)
+        if (p->ax[a].n > 1) {
+            last = a;
+            nsel *= (double)p->ax[a].n;
+        }
+    PassArgs ev{};
+    ev.ev_d = p->ny;
+    ev.ev_la = (int)p->nx;
+    ev.ev_lb = (int)p->ny;
+    for (int j0 = 0; j0 < nsteps; j0 += FB_MAX_FUSED_STEPS) {
+        const int k = nsteps - j0 < FB_MAX_FUSED_STEPS ? nsteps - j0 : FB_MAX_FUSED_STEPS;
+        MultiOut m{};
+        m.nout = k;
+        for (int i = 0; i < k; i++) m.cs[i] = evolve_c(alpha, t[j0 + i]);
+        char *xo = (char *)x_out + gbytes * j0;
+        // z: evolve + inverse DFT of the spectrum into k grids; then y and x over all k grids
+        int rc = launch_axis(p, 0, uhat0, xo, 1, last == 0 ? 1.0 / nsel : 1.0, &ev, st, nullptr, 1, &m);
+        for (int a = 1; !rc && a < 3; a++)
+            if (p->ax[a].n > 1) rc = launch_axis(p, a, xo, xo, 1, a == last ? 1.0 / nsel : 1.0, nullptr, st, nullptr, k);
+        if (rc) return (fb_status)rc;
+        if (sums_dev) {
+            hipError_t e = timed_launch(p->esize == 16 ? "checksum<c128>" : "checksum<c64>",
+                                        (1024.0 * p->esize + 16) * k, st,
+                                        [&] { return fb::launch_checksum(p->esize, xo, p->N, sums_dev + 2 * j0, st, k); });
+            if (e != hipSuccess) return (fb_status)hip_fail(e, "checksum launch");
+        }
     }
     return (fb_status)ok();
 }

@@ -9,6 +9,9 @@
 namespace fb {
 
 // Arguments of one pencil pass (see fb_pass.hpp for the geometry).
+// Evolution steps one multi-output pass computes from one read of the spectrum.
+#define FB_MAX_FUSED_STEPS 8
+
 struct PassArgs {
     const void *in;
     void *out;
@@ -50,6 +53,12 @@ struct PassArgs {
     double ev_c;
     int64_t ev_d;
     int ev_la, ev_lb;
+    // several evolution steps from one read of the spectrum (contiguous
+    // evolve passes of the multi-output kernel): output j (j < nout) is the
+    // pass applied with evolution constant ev_cs[j], written at out + j out_step
+    int nout;
+    int64_t out_step;
+    double ev_cs[FB_MAX_FUSED_STEPS];
 };
 
 using PassLauncher = hipError_t (*)(const PassArgs &, hipStream_t);
@@ -67,6 +76,10 @@ struct PassInfo {
 // no such variant exists).  Returns launch == nullptr when the length has no
 // instantiated pass.
 PassInfo find_pass(int esize, int n, bool contig, bool mx);
+
+// Contiguous evolve pass with up to FB_MAX_FUSED_STEPS outputs from one read
+// of its input (PassArgs::nout); mx as for find_pass.
+PassInfo find_pass_multi(int esize, int n, bool mx);
 
 // Strided complex64 pass that moves two adjacent pencils per 16-byte access
 // (needs an even number of pencils, pencil pairs adjacent in memory
@@ -92,7 +105,8 @@ hipError_t launch_evolve(int esize, const void *in, void *out, int64_t nx, int64
                          double c, hipStream_t st);
 
 // out2[0] + i out2[1] = sum_{j<1024} x[(17 j) mod N], fixed-order binary64 tree.
-hipError_t launch_checksum(int esize, const void *x, int64_t N, double *out2, hipStream_t st);
+// Checksums of `count` consecutive grids of N elements into out2[2g], out2[2g+1].
+hipError_t launch_checksum(int esize, const void *x, int64_t N, double *out2, hipStream_t st, int count = 1);
 
 // x[i] = U(seed, 2i) + i U(seed, 2i+1)  (SplitMix64, counter based)
 hipError_t launch_fill_uniform(int esize, void *x, int64_t N, uint64_t seed, hipStream_t st);

@@ -11,6 +11,15 @@ namespace fb {
 
 PassInfo find_pass_c128(int n, bool contig, bool mx);
 PassInfo find_pass_c64(int n, bool contig, bool mx);
+PassInfo find_pass_multi_c128(int n);
+PassInfo find_pass_multi_c64(int n, bool mx);
+
+PassInfo find_pass_multi(int esize, int n, bool mx)
+{
+    if (esize == 16) return find_pass_multi_c128(n);
+    if (esize == 8) return find_pass_multi_c64(n, mx);
+    return {nullptr, 0, 0, 0};
+}
 
 PassInfo find_pass(int esize, int n, bool contig, bool mx)
 {
@@ -121,11 +130,14 @@ hipError_t launch_evolve(int esize, const void *in, void *out, int64_t nx, int64
 // ---------------------------------------------------------------- checksum
 
 // 1024 threads; thread j loads x[(17 j) mod N]; pairwise tree in binary64.
+// Workgroup g sums grid g of `count` consecutive grids into out2[2g], out2[2g+1].
 template <typename V>
 __global__ void __launch_bounds__(1024) checksum_kernel(const V *x, int64_t N, double *out2)
 {
     __shared__ double sr[1024], si[1024];
     const int j = threadIdx.x;
+    x += (int64_t)blockIdx.x * N;
+    out2 += 2 * (int64_t)blockIdx.x;
     const V v = x[(17 * (int64_t)j) % N];
     sr[j] = (double)v.x;
     si[j] = (double)v.y;
@@ -143,12 +155,13 @@ __global__ void __launch_bounds__(1024) checksum_kernel(const V *x, int64_t N, d
     }
 }
 
-hipError_t launch_checksum(int esize, const void *x, int64_t N, double *out2, hipStream_t st)
+hipError_t launch_checksum(int esize, const void *x, int64_t N, double *out2, hipStream_t st, int count)
 {
+    if (count <= 0) return hipSuccess;
     if (esize == 16)
-        hipLaunchKernelGGL((checksum_kernel<double2>), dim3(1), dim3(1024), 0, st, (const double2 *)x, N, out2);
+        hipLaunchKernelGGL((checksum_kernel<double2>), dim3(count), dim3(1024), 0, st, (const double2 *)x, N, out2);
     else
-        hipLaunchKernelGGL((checksum_kernel<float2>), dim3(1), dim3(1024), 0, st, (const float2 *)x, N, out2);
+        hipLaunchKernelGGL((checksum_kernel<float2>), dim3(count), dim3(1024), 0, st, (const float2 *)x, N, out2);
     return hipGetLastError();
 }
 

@@ -317,7 +317,7 @@ __device__ __forceinline__ void store_tile_contiguous(const PassArgs &a, int64_t
 // `gtab` N reals (contiguous passes).  The caller may run the tile on a
 // workgroup larger than the tile's THREADS (the persistent batch kernel):
 // the extra threads only take part in the barriers.
-template <typename V, int N, bool CONTIG, bool MX>
+template <typename V, int N, bool CONTIG, bool MX, bool MULTI = false>
 __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int tid, V *lds, real_t<V> *gtab)
 {
     using Cfg = PassCfg<V, N, CONTIG>;
@@ -328,6 +328,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
     static_assert(!MX || mx_capable<V, N, CONTIG>(), "no matrix-core variant for this pass");
     constexpr bool PAIR = std::is_same<V, c2x>::value;   // each unit is two adjacent pencils
     static_assert(!PAIR || !CONTIG, "pencil pairs are for strided passes");
+    static_assert(!MULTI || CONTIG, "multi-output passes are contiguous evolve passes");
     using E = elem_t<V>;
     using TW = tw_t<V>;
 
@@ -352,48 +353,80 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
     V *row = lds + (active ? pp : 0) * LS;
 
     V v[M];
+    [[maybe_unused]] V v0[MULTI ? M : 1];   // the loaded spectrum, kept for every output
 
-    // ---- optional fused evolution factor along the pencil (contiguous only)
+    using MXS = MxStage<V, N, CONTIG, MX>;
+    // first / last matrix-core stage reads / writes global memory itself
+    constexpr bool MX_IN = MXS::at(0) && MXS::direct() && !MULTI;
+    constexpr bool MX_OUT = MXS::at(NST - 1) && MXS::direct() && !MULTI;
+    constexpr int R0 = RP.r[0];
+    constexpr int NBF0 = N / R0;
+    constexpr int U0 = (NBF0 + T - 1) / T;
+
+    // ---- optional fused evolution factor (contiguous only): a table along
+    // the pencil times a factor of the pencil's own two wavenumbers.  A
+    // single-output pass builds it before its loads (fewer live registers);
+    // a multi-output pass once per output.
     R gab = (R)1;
-    if constexpr (CONTIG) {
-        if (a.evolve) {
-            for (int i = tid; active && i < N; i += Cfg::THREADS) {
-                const double k = (double)signed_k(i, N);
-                gtab[i] = evol_factor<R>(a.ev_c, k * k);
+    [[maybe_unused]] auto evolve_factors = [&](double c) {
+        for (int i = tid; active && i < N; i += Cfg::THREADS) {
+            const double k = (double)signed_k(i, N);
+            gtab[i] = evol_factor<R>(c, k * k);
+        }
+        if (valid) {
+            const int64_t pa = p / a.ev_d, pb = p % a.ev_d;
+            const double ka = (double)signed_k(pa, a.ev_la), kb = (double)signed_k(pb, a.ev_lb);
+            gab = evol_factor<R>(c, ka * ka + kb * kb);
+        }
+        __syncthreads();
+    };
+    if constexpr (CONTIG && !MULTI) {
+        if (a.evolve) evolve_factors(a.ev_c);
+    }
+
+    // ---- stage 0 input: global loads (or generated values), pattern b + q N/R0
+    if (valid && !MX_IN) {
+#pragma unroll
+        for (int u = 0; u < U0; u++) {
+            const int b = t + T * u;
+            if (NBF0 % T == 0 || b < NBF0) {
+                if (a.gen) {
+#pragma unroll
+                    for (int q = 0; q < R0; q++)
+                        v[u * R0 + q] = uniform_elem<V>(a.gen_seed, (uint64_t)(base + (int64_t)(b + q * NBF0) * S));
+                } else {
+#pragma unroll
+                    for (int q = 0; q < R0; q++) v[u * R0 + q] = ld_v<V>(gin + (int64_t)(b + q * NBF0) * S);
+                }
             }
-            if (valid) {
-                const int64_t pa = p / a.ev_d, pb = p % a.ev_d;
-                const double ka = (double)signed_k(pa, a.ev_la), kb = (double)signed_k(pb, a.ev_lb);
-                gab = evol_factor<R>(a.ev_c, ka * ka + kb * kb);
-            }
-            __syncthreads();
+        }
+    }
+    if constexpr (MULTI) {
+#pragma unroll
+        for (int i = 0; i < M; i++) v0[i] = v[i];
+    }
+
+    [[maybe_unused]] MxConsts mxc;
+    if constexpr (MX) mxc = mx_consts(tid & 63);
+
+    auto body = [&](int rep) {
+    if constexpr (MULTI) {
+        if (rep > 0) {
+#pragma unroll
+            for (int i = 0; i < M; i++) v[i] = v0[i];
+            __syncthreads();   // the previous output's LDS and factor-table readers are done
         }
     }
 
-    using MXS = MxStage<V, N, CONTIG, MX>;
-    constexpr bool MX_IN = MXS::at(0) && MXS::direct();         // first stage loads global itself
-    constexpr bool MX_OUT = MXS::at(NST - 1) && MXS::direct();  // last stage stores global itself
+    if constexpr (MULTI) {
+        if (a.evolve) evolve_factors(a.ev_cs[rep]);
+    }
 
-    // ---- stage 0 input: global loads, pattern b + q N/R0
+    // ---- stage 0 input: evolution factor, conjugation, pre-twiddle
     {
-        constexpr int R0 = RP.r[0];
-        constexpr int NBF = N / R0;
-        constexpr int U = (NBF + T - 1) / T;
+        constexpr int NBF = NBF0;
+        constexpr int U = U0;
         if (valid && !MX_IN) {
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                const int b = t + T * u;
-                if (NBF % T == 0 || b < NBF) {
-                    if (a.gen) {
-#pragma unroll
-                        for (int q = 0; q < R0; q++)
-                            v[u * R0 + q] = uniform_elem<V>(a.gen_seed, (uint64_t)(base + (int64_t)(b + q * NBF) * S));
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < R0; q++) v[u * R0 + q] = ld_v<V>(gin + (int64_t)(b + q * NBF) * S);
-                    }
-                }
-            }
             if constexpr (CONTIG) {
                 if (a.evolve) {
 #pragma unroll
@@ -438,9 +471,6 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
             __syncthreads();
         }
     }
-
-    [[maybe_unused]] MxConsts mxc;
-    if constexpr (MX) mxc = mx_consts(tid & 63);
 
     static_for<0, NST>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
@@ -569,6 +599,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
         }
         if (valid && !MX_OUT) {
             const R sc = (R)a.scale;
+            E *__restrict__ go = MULTI ? gout + rep * a.out_step : gout;
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int b = t + T * u;
@@ -580,16 +611,22 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                         if (a.scale != 1.0) o = cscale(o, sc);
                         if constexpr (PAIR) {
                             if (a.opair_step) {   // the pair's outputs are not adjacent
-                                st_stream(gout + (int64_t)(b + q * NBF) * OS, o.a);
-                                st_stream(gout + (int64_t)(b + q * NBF) * OS + a.opair_step, o.b);
+                                st_stream(go + (int64_t)(b + q * NBF) * OS, o.a);
+                                st_stream(go + (int64_t)(b + q * NBF) * OS + a.opair_step, o.b);
                                 continue;
                             }
                         }
-                        st_v<V>(gout + (int64_t)(b + q * NBF) * OS, o);
+                        st_v<V>(go + (int64_t)(b + q * NBF) * OS, o);
                     }
                 }
             }
         }
+    }
+    };   // outputs
+    if constexpr (MULTI) {
+        for (int rep = 0; rep < a.nout; rep++) body(rep);
+    } else {
+        body(0);
     }
 }
 
@@ -600,6 +637,18 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) FB_OCCUPANCY
     __shared__ V lds[Cfg::P * Cfg::LS];
     __shared__ real_t<V> gtab[CONTIG ? N : 1];
     pass_tile<V, N, CONTIG, MX>(a, blockIdx.x, threadIdx.x, lds, gtab);
+}
+
+// Contiguous evolve pass with several outputs: the tile's spectrum is read
+// once and output j (evolution constant ev_cs[j]) is written at
+// out + j out_step, for j < nout.
+template <typename V, int N, bool MX>
+__global__ void __launch_bounds__((PassCfg<V, N, true>::THREADS)) FB_OCCUPANCY fft_pass_multi(PassArgs a)
+{
+    using Cfg = PassCfg<V, N, true>;
+    __shared__ V lds[Cfg::P * Cfg::LS];
+    __shared__ real_t<V> gtab[N];
+    pass_tile<V, N, true, MX, true>(a, blockIdx.x, threadIdx.x, lds, gtab);
 }
 
 }  // namespace fb

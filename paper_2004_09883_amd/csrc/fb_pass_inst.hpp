@@ -58,6 +58,36 @@ inline PassInfo find_pass_pair_t(int n, bool mx)
     }
 }
 
+template <typename V, int N, bool MX> hipError_t launch_pass_multi(const PassArgs &a, hipStream_t st)
+{
+    using Cfg = PassCfg<V, N, true>;
+    const int64_t blocks = (a.npencils + Cfg::P - 1) / Cfg::P;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((fft_pass_multi<V, N, MX>), dim3((unsigned)blocks), dim3(Cfg::THREADS), 0, st, a);
+    return hipGetLastError();
+}
+
+// Contiguous multi-output evolve passes (the matrix-core variant where one
+// exists and MX is asked for).
+template <typename V, int N> PassInfo pass_info_multi(bool mx)
+{
+    using Cfg = PassCfg<V, N, true>;
+    if constexpr (mx_capable<V, N, true>()) {
+        if (mx) return {&launch_pass_multi<V, N, true>, Cfg::P, Cfg::THREADS, 1};
+    }
+    return {&launch_pass_multi<V, N, false>, Cfg::P, Cfg::THREADS, 0};
+}
+
+template <typename V> PassInfo find_pass_multi_t(int n, bool mx)
+{
+    switch (n) {
+#define FB_CASE(L) case L: return pass_info_multi<V, L>(mx);
+        FB_FOR_EACH_LENGTH(FB_CASE)
+#undef FB_CASE
+    default: return {nullptr, 0, 0, 0};
+    }
+}
+
 template <typename V> PassInfo find_pass_t(int n, bool contig, bool mx)
 {
     switch (n) {

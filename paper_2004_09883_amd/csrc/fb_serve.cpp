@@ -63,9 +63,9 @@ struct Slot {
     int64_t id = -1;
     fb_request req{};
     double t_arrival = 0, t_admit = 0;
-    void *u0 = nullptr, *x = nullptr;      // device grids
+    void *u0 = nullptr, *x = nullptr;      // device grids: the spectrum, the output grids of a chunk of steps
     double *sums_dev = nullptr;            // device checksums
-    size_t grid_bytes = 0, sums_bytes = 0;
+    size_t grid_bytes = 0, x_bytes = 0, sums_bytes = 0;
     size_t charged = 0;                    // bytes charged to the budget
     double *sums_host = nullptr;           // pinned, FB_SERVE_MAX_STEPS checksums, owned by the slot
     void *grid_host = nullptr;             // pinned (when the final grid is wanted)
@@ -104,11 +104,19 @@ namespace {
 
 size_t esize_of(int dtype) { return dtype == FB_C128 ? 16 : 8; }
 
-// Device bytes a request holds while admitted: two grids and its checksums.
+// Steps computed together from one read of the spectrum (fb_spectral_steps):
+// a request holds this many output grids.
+constexpr int kChunk = 8;
+int chunk_of(int steps) { return steps < kChunk ? steps : kChunk; }
+
+size_t sums_bytes_of(int steps) { return 256 * ((size_t)(16 * steps + 255) / 256); }
+
+// Device bytes a request holds while admitted: the spectrum, the output
+// grids of one chunk of steps and its checksums.
 size_t request_bytes(const fb_request &r)
 {
     const size_t n = (size_t)(r.nx * r.ny * r.nz);
-    return 2 * n * esize_of(r.dtype) + 256 * ((size_t)(16 * r.steps + 255) / 256);
+    return (1 + (size_t)chunk_of(r.steps)) * n * esize_of(r.dtype) + sums_bytes_of(r.steps);
 }
 
 void *pool_get(fb_server *s, size_t bytes, hipError_t &e)
@@ -139,16 +147,13 @@ void pool_put(fb_server *s, size_t bytes, void *p)
     if (p) s->pool.emplace(bytes, p);
 }
 
-size_t sums_bytes_of(int steps) { return 256 * ((size_t)(16 * steps + 255) / 256); }
-
 // Admission test: the device bytes in use by admitted requests plus what r
 // needs must fit in the budget (pooled free buffers can always be released).
 bool fits(fb_server *s, const fb_request &r)
 {
     size_t in_use = s->bytes_allocated;
     for (auto &kv : s->pool) in_use -= kv.first;
-    const size_t need = 2 * (size_t)(r.nx * r.ny * r.nz) * esize_of(r.dtype) + sums_bytes_of(r.steps);
-    return in_use + need <= s->budget;
+    return in_use + request_bytes(r) <= s->budget;
 }
 
 fb_plan *plan_for(fb_server *s, const fb_request &r)
@@ -182,7 +187,7 @@ void finish(fb_server *s, Slot &sl, int status)
         }
     }
     pool_put(s, sl.grid_bytes, sl.u0);
-    pool_put(s, sl.grid_bytes, sl.x);
+    pool_put(s, sl.x_bytes, sl.x);
     pool_put(s, sl.sums_bytes, sl.sums_dev);
     if (sl.grid_host) (void)hipHostFree(sl.grid_host);
     sl.u0 = sl.x = nullptr;
@@ -201,21 +206,31 @@ int launch(fb_server *s, Slot &sl)
     fb_plan *p = plan_for(s, r);
     if (!p) return fb_last_error(nullptr);
     hipError_t e = hipSuccess;
+    const int chunk = chunk_of(r.steps);
     sl.grid_bytes = (size_t)(r.nx * r.ny * r.nz) * esize_of(r.dtype);
+    sl.x_bytes = (size_t)chunk * sl.grid_bytes;
     sl.sums_bytes = sums_bytes_of(r.steps);
     sl.u0 = pool_get(s, sl.grid_bytes, e);
-    if (e == hipSuccess) sl.x = pool_get(s, sl.grid_bytes, e);
+    if (e == hipSuccess) sl.x = pool_get(s, sl.x_bytes, e);
     if (e == hipSuccess) sl.sums_dev = (double *)pool_get(s, sl.sums_bytes, e);
     if (e == hipSuccess && r.want_grid) e = hipHostMalloc(&sl.grid_host, sl.grid_bytes, hipHostMallocDefault);
     if (e != hipSuccess) return FB_ERR_OOM;
     const uint64_t seed = splitmix64_at(r.seed, (uint64_t)r.request_key);
     int rc = fb_fft3d_forward_uniform(p, seed, sl.u0, sl.stream);
-    for (int t = 1; !rc && t <= r.steps; t++)
-        rc = fb_spectral_step(p, sl.u0, sl.x, r.alpha, (double)t, sl.sums_dev + 2 * (t - 1), sl.stream);
+    // steps t = 1..steps in chunks: each chunk reads the spectrum once
+    double ts[kChunk];
+    int last = 0;   // grid of the final step within the buffer
+    for (int j0 = 0; !rc && j0 < r.steps; j0 += chunk) {
+        const int k = r.steps - j0 < chunk ? r.steps - j0 : chunk;
+        for (int i = 0; i < k; i++) ts[i] = (double)(j0 + i + 1);
+        rc = fb_spectral_steps(p, sl.u0, sl.x, r.alpha, ts, k, sl.sums_dev + 2 * j0, sl.stream);
+        last = k - 1;
+    }
     if (rc) return rc;
     e = hipMemcpyAsync(sl.sums_host, sl.sums_dev, 16 * (size_t)r.steps, hipMemcpyDeviceToHost, sl.stream);
     if (e == hipSuccess && sl.grid_host)
-        e = hipMemcpyAsync(sl.grid_host, sl.x, sl.grid_bytes, hipMemcpyDeviceToHost, sl.stream);
+        e = hipMemcpyAsync(sl.grid_host, (const char *)sl.x + (size_t)last * sl.grid_bytes, sl.grid_bytes,
+                           hipMemcpyDeviceToHost, sl.stream);
     if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
     return e == hipSuccess ? FB_OK : FB_ERR_DEVICE;
 }

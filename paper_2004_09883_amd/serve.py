@@ -20,13 +20,15 @@ HBM_PEAK_GBS = 8000.0
 
 
 def request_model_bytes(shape, is_c64: bool, steps: int) -> float:
-    """Bytes a request moves under the pencil-pass model: every 3D transform
-    reads and writes the grid once per pass (3 passes); the input is
-    generated inside the first forward pass (it writes only), the evolution
-    is fused into the first inverse pass."""
+    """Bytes a request moves under the pencil-pass model: every pass reads
+    and writes the grid once; the forward transform's first pass generates
+    its input (writes only); the steps share their first inverse pass (with
+    the evolution fused in) in chunks of up to 8, which read the spectrum
+    once and write one grid per step."""
     n = math.prod(shape)
     e = 8 if is_c64 else 16
-    return (1 + steps) * 3 * 2 * e * n - e * n
+    chunks = (steps + 7) // 8
+    return e * n * (5 + chunks + steps * 5)
 
 
 def request_flops(shape, steps: int) -> float:

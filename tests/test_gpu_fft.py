@@ -189,6 +189,50 @@ def test_forward_uniform_equals_fill_then_exec(dtype, shape):
 
 # ---------------------------------------------------------------- the spectral block
 
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("shape,ts", [((16, 32, 64), list(range(1, 12))), ((6, 96, 1), [1, 2, 3]),
+                                      ((1, 1, 256), [0.0, 2.5, 7.0]), ((12, 8, 48), [3.0] * 9),
+                                      ((64, 64, 64), [1, 2, 3, 4, 5, 6])])
+def test_spectral_steps_equal_single_steps(dtype, shape, ts):
+    """Several steps from one read of the spectrum give, bit for bit, the
+    grids and checksums of one fb_spectral_step per t (chunks of up to 8
+    outputs per fused pass, ragged last chunk, nz = 1 fallback, repeated t);
+    and they match the oracle."""
+    alpha = 1e-3 if shape[0] < 64 else 1e-6
+    plan = fb.Plan(*shape, dtype)
+    x0 = as_seen(inputs.uniform_grid(shape, 21), dtype)
+    u0 = dev(x0, dtype)
+    fb.fb_fft3d_exec(plan, u0, u0, fb.FB_FORWARD)
+    nt = len(ts)
+    multi = torch.full((nt,) + shape, 3.0, dtype=plan.torch_dtype, device="cuda")
+    msums = torch.zeros((nt, 2), dtype=torch.float64, device="cuda")
+    fb.fb_spectral_steps(plan, u0, multi, alpha, ts, msums)
+    one = torch.empty(shape, dtype=plan.torch_dtype, device="cuda")
+    osums = torch.zeros((nt, 2), dtype=torch.float64, device="cuda")
+    for j, t in enumerate(ts):
+        fb.fb_spectral_step(plan, u0, one, alpha, float(t), osums[j])
+        assert torch.equal(one, multi[j]), (j, t)
+    assert torch.equal(osums, msums)
+    X0 = oracle.fft3d(x0, -1)
+    tol = 1e-12 if dtype == fb.FB_C128 else 1e-5
+    for j in (0, nt - 1):
+        ref = oracle.fft3d(oracle.evolve(X0, alpha, float(ts[j])), +1)
+        assert rel_l2(host(multi[j]), ref) < tol, j
+
+
+def test_spectral_steps_rejects_bad_arguments():
+    plan = fb.Plan(8, 8, 8, fb.FB_C128)
+    u0 = torch.zeros((8, 8, 8), dtype=torch.complex128, device="cuda")
+    out = torch.zeros((2, 8, 8, 8), dtype=torch.complex128, device="cuda")
+    for ts in ([], [1.0, -1.0], [float("nan")]):
+        with pytest.raises(fb.FbError):
+            fb.fb_spectral_steps(plan, u0, out[: max(1, len(ts))] if ts else out[:1], 1e-6, ts)
+    # x_out overlapping uhat0
+    with pytest.raises(fb.FbError):
+        fb.fb_spectral_steps(plan, out[1], out, 1e-6, [1.0, 2.0])
+
+
 def spectral_block_gpu(x0, dtype, alpha, steps, fused=True):
     shape = x0.shape
     plan = fb.Plan(*shape, dtype)
@@ -368,3 +412,17 @@ def test_graph_replays_match_eager():
         assert torch.equal(sums, want_sums), r
         assert torch.equal(xt, want_x), r
         del other
+
+
+def test_offload_pattern_search():
+    """The verification search of the paper's method on a small block: all
+    16 placements of (forward, evolve, inverse, checksum) run end to end with
+    the host/device copies they need, and every one gives the all-device
+    checksums (host blocks in numpy, device blocks through libfb)."""
+    from paper_2004_09883_amd import offload
+    rep = offload.search(torch, fb, shape=(32, 32, 32), alpha=1e-3, steps=2)
+    print("offload search:", {k: rep[k] for k in ("greedy_pattern", "best_pattern", "x_vs_all_cpu")}, flush=True)
+    assert len(rep["patterns"]) == 16
+    assert rep["max_checksum_rel_err"] < 1e-12
+    assert rep["best_seconds"] <= rep["all_cpu_seconds"]
+    assert set(rep["greedy_pattern"]) <= {"C", "G"} and len(rep["greedy_pattern"]) == 4

@@ -2,6 +2,8 @@
 and in a mix of concurrent requests (bitwise: the kernels and their order do
 not depend on the mix), results match the oracle, and admission never lets
 device memory exceed the HBM budget."""
+import math
+
 import numpy as np
 import pytest
 
@@ -84,7 +86,8 @@ def test_alone_equals_mix_and_oracle():
 
 
 def test_budget_admission():
-    one = 2 * nbytes((128, 128, 128), fb.FB_C128) + 4096
+    # a request holds its spectrum and min(steps, 8) output grids
+    one = 9 * nbytes((128, 128, 128), fb.FB_C128) + 4096
     server = fb.Server(one, 4)
     for k in range(5):
         server.submit(128, 128, 128, fb.FB_C128, 10, ALPHA, SEED, 50 + k)
@@ -115,3 +118,45 @@ def test_short_serving_run():
     print("serving:", rep, flush=True)
     assert rep["failed"] == 0 and rep["requests"] > 200
     assert 0 < rep["p50_ms"] <= rep["p99_ms"]
+
+
+def test_serving_workload_sample_against_oracle():
+    """The first 160 requests of the serving workload (Poisson stream of
+    seed 5: shapes, dtypes, step counts; inputs from seed 4 and the request
+    index), submitted at once so that the loop runs them concurrently; every
+    32^3 and 64^3 request and one in forty of the others is checked against
+    the oracle (checksums of the first and the last step)."""
+    count = 160
+    w = inputs.serving_workload(count, 2000.0, 5)
+    server = fb.Server(int(200e9), 8)
+    ids = {}
+    for j in range(count):
+        shape = inputs.SERVING_SHAPES[int(w["shape"][j])]
+        dt = fb.FB_C64 if bool(w["is_c64"][j]) else fb.FB_C128
+        steps = int(w["steps"][j])
+        ids[server.submit(*shape, dt, steps, ALPHA, SEED, j)] = (j, shape, dt, steps)
+    got = wait_for(server, count, 0)
+    info = server.stats()
+    server.close()
+    assert info["max_concurrent"] > 1
+    others = checked = 0
+    for rid, (j, shape, dt, steps) in sorted(ids.items()):
+        r = got[rid]
+        assert r["status"] == 0, j
+        if math.prod(shape) > 64 ** 3:
+            others += 1
+            if others % 40 != 1:
+                continue
+        x0 = inputs.request_grid(shape, SEED, j)
+        if dt == fb.FB_C64:
+            x0 = inputs.round_c64(x0).astype(np.complex128)
+        X0 = oracle.fft3d(x0, -1)
+        tol = 1e-12 if dt == fb.FB_C128 else 1e-5
+        for t in sorted({1, steps}):
+            ref = oracle.fft3d(oracle.evolve(X0, ALPHA, t), +1)
+            flat = ref.reshape(-1)
+            norm = np.sum(np.abs(flat[(17 * np.arange(1024)) % flat.size]))
+            assert abs(r["checksums"][t - 1] - oracle.checksum(ref)) / norm < tol, (j, t)
+        checked += 1
+    print(f"serving workload sample: {checked} of {count} requests checked against the oracle", flush=True)
+    assert checked >= 10
