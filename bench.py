@@ -521,6 +521,12 @@ def main() -> int:
         rec["block_64x64x64"] = small_block_section(torch, fb)
         from paper_2004_09883_amd import offload
         rec["offload_search_64x64x64"] = offload.search(torch, fb, shape=(64, 64, 64), alpha=ALPHA, steps=6)
+        import shutil
+        if shutil.which("gcc"):
+            from paper_2004_09883_amd import substitute_run
+            rec["substitution_heat3d"] = substitute_run.heat3d_experiment()
+        else:
+            rec["substitution_heat3d"] = {"skipped": "gcc not available"}
         rec["forms_512x256x256"] = forms_section(torch, fb)
         rec["batched"] = batched_section(torch, fb)
         rec["paper_2d_2048"] = paper_2d_section(torch, fb)

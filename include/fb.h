@@ -102,6 +102,15 @@ const char *fb_plan_describe(const fb_plan *p);
  * partially overlapping buffers are rejected.  Needs no workspace. */
 fb_status fb_fft3d_exec(const fb_plan *p, const void *in, void *out, int dir, void *hip_stream);
 
+/* The same transform on HOST buffers, synchronously: the grid is copied to a
+ * device buffer the call allocates, transformed in place there and copied
+ * back (in_host == out_host allowed).  This is the drop-in form of a CPU
+ * library call "of the same meaning" (section 3.4, C-1: the replaced call
+ * keeps the host program's data where it was); its cost includes both PCIe
+ * copies and an allocation, so streamed device-resident use goes through
+ * fb_fft3d_exec.  Errors as fb_fft3d_exec, plus FB_ERR_OOM. */
+fb_status fb_fft3d_exec_host(const fb_plan *p, const void *in_host, void *out_host, int dir);
+
 /* The same transform restricted to some axes: bit 0 of `axes` selects z,
  * bit 1 y, bit 2 x (axes = 7 is fb_fft3d_exec).  The inverse divides by the
  * product of the selected lengths.  With no axis of length > 1 selected the

@@ -40,6 +40,8 @@ def _load():
     lib = ctypes.CDLL(_LIB)
     i64, dp, i32 = ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_int
     lib.orc_threads.restype = i32
+    lib.orc_lu.argtypes = [i64, i64, dp, ctypes.POINTER(i32)]
+    lib.orc_lu.restype = i32
     lib.orc_set_threads.argtypes = [i32]
     lib.orc_radices.argtypes = [i64, ctypes.POINTER(i32), i32]
     lib.orc_describe.argtypes = [i64, i64, i64, ctypes.c_char_p, i32]
@@ -185,3 +187,20 @@ def spectral_block(x0, alpha: float, steps: int, keep=None):
         if t in keep:
             grids[t] = xt
     return np.array(sums), grids
+
+
+def lu(a):
+    """LU with partial pivoting of a square matrix (the paper's LU block,
+    section 5.1(b)): returns (lu, ipiv, info) with the unit lower factor below
+    the diagonal and the upper factor on and above it, row-major; ipiv[j] is
+    the row swapped with row j at step j (0-based)."""
+    m = np.ascontiguousarray(np.array(a, dtype=np.float64))
+    if m.ndim != 2 or m.shape[0] != m.shape[1]:
+        raise ValueError("expected a square matrix")
+    n = m.shape[0]
+    ipiv = np.zeros(max(1, n), dtype=np.int32)
+    info = _load().orc_lu(n, n, m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          ipiv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if info < 0:
+        raise ValueError("bad arguments")
+    return m, ipiv[:n], int(info)

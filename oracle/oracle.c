@@ -21,6 +21,9 @@
  *
  * Grids are C order [nx][ny][nz] (z contiguous), interleaved re/im binary64.
  *
+ * Also the paper's other function block (section 5.1(b)), an LU
+ * factorization with partial pivoting (orc_lu, at the end of this file).
+ *
  * Two tiers:
  *   orc_dft3d_brute  the definition: a direct triple sum in long double with
  *                    exact integer phase reduction (tiny grids only);
@@ -398,4 +401,57 @@ int orc_checksum(int64_t nx, int64_t ny, int64_t nz, const double *x, double *ou
     out[0] = sr;
     out[1] = si;
     return 0;
+}
+
+/* ------------------------------------------------------------------ LU
+ * The paper's second function block (section 5.1(b)): an LU factorization,
+ * here the definition of Gaussian elimination with partial pivoting on a
+ * row-major n x n binary64 matrix (row stride lda), in place:
+ *
+ *   for j = 0 .. n-1:
+ *     p = the first row i >= j with the largest |a[i][j]|
+ *     ipiv[j] = p; swap rows j and p (all n columns)
+ *     if a[j][j] != 0: for i > j: a[i][j] /= a[j][j];
+ *                      for i > j, c > j: a[i][c] -= a[i][j] * a[j][c]
+ *     else: info = j + 1 for the first such j (the column is left as it is)
+ *
+ * so that P A = L U with L unit lower triangular (below the diagonal) and U
+ * upper triangular (on and above it), P the product of the swaps in order.
+ * Returns info (0: all pivots non-zero), or -1 on bad arguments.  The
+ * trailing updates of one step are independent per row (OpenMP over rows);
+ * each element receives its updates in increasing j. */
+int orc_lu(int64_t n, int64_t lda, double *a, int32_t *ipiv)
+{
+    if (n < 0 || lda < n || (n > 0 && (!a || !ipiv))) return -1;
+    int info = 0;
+    for (int64_t j = 0; j < n; j++) {
+        int64_t p = j;
+        double best = fabs(a[j * lda + j]);
+        for (int64_t i = j + 1; i < n; i++) {
+            const double v = fabs(a[i * lda + j]);
+            if (v > best) {
+                best = v;
+                p = i;
+            }
+        }
+        ipiv[j] = (int32_t)p;
+        if (p != j)
+            for (int64_t c = 0; c < n; c++) {
+                const double t = a[j * lda + c];
+                a[j * lda + c] = a[p * lda + c];
+                a[p * lda + c] = t;
+            }
+        const double piv = a[j * lda + j];
+        if (piv == 0.0) {
+            if (!info) info = (int)(j + 1);
+            continue;
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t i = j + 1; i < n; i++) {
+            const double l = a[i * lda + j] / piv;
+            a[i * lda + j] = l;
+            for (int64_t c = j + 1; c < n; c++) a[i * lda + c] -= l * a[j * lda + c];
+        }
+    }
+    return info;
 }

@@ -486,6 +486,28 @@ fb_status fb_fft3d_exec(const fb_plan *p, const void *in, void *out, int dir, vo
     return (fb_status)ok();
 }
 
+fb_status fb_fft3d_exec_host(const fb_plan *p, const void *in_host, void *out_host, int dir)
+{
+    if (check_plan(p)) return (fb_status)g_code;
+    if (!in_host || !out_host) return (fb_status)fail(FB_ERR_INVALID_ARG, "in_host / out_host is NULL");
+    if (dir != FB_FORWARD && dir != FB_INVERSE)
+        return (fb_status)fail(FB_ERR_INVALID_ARG, "dir must be FB_FORWARD (-1) or FB_INVERSE (+1), got %d", dir);
+    if (check_device(p)) return (fb_status)g_code;
+    const size_t bytes = (size_t)p->N * (size_t)p->esize;
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) return (fb_status)fail(FB_ERR_OOM, "hipMalloc of %zu bytes failed", bytes);
+    e = hipMemcpy(d, in_host, bytes, hipMemcpyHostToDevice);
+    int rc = e != hipSuccess ? hip_fail(e, "host-to-device copy") : run_passes(p, d, d, dir, nullptr, nullptr);
+    if (!rc) {
+        e = hipMemcpy(out_host, d, bytes, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = hip_fail(e, "device-to-host copy");
+    }
+    (void)hipFree(d);
+    if (rc) return (fb_status)rc;
+    return (fb_status)ok();
+}
+
 fb_status fb_fft3d_exec_axes(const fb_plan *p, const void *in, void *out, int dir, int axes, void *hip_stream)
 {
     if (check_plan(p) || check_grid_ptr(p, in, "in") || check_grid_ptr(p, out, "out")) return (fb_status)g_code;

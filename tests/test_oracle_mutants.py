@@ -27,6 +27,10 @@ MUTANTS = {
                       "if (fft_axis(data, ny, nz, nx * nz, nz, 1, nx * nz, sign))"),
     "direct_dft_index": ("acc = cadd(acc, cmul(x[q * s], tw_at(p, len, q * k)));",
                          "acc = cadd(acc, cmul(x[q], tw_at(p, len, q * k)));"),
+    "lu_last_max_pivot": ("            if (v > best) {", "            if (v >= best) {"),
+    "lu_partial_row_swap": ("            for (int64_t c = 0; c < n; c++) {\n                const double t = a[j * lda + c];",
+                            "            for (int64_t c = j; c < n; c++) {\n                const double t = a[j * lda + c];"),
+    "lu_update_wrong_row": ("a[i * lda + c] -= l * a[j * lda + c];", "a[i * lda + c] -= l * a[i * lda + c - 1];"),
 }
 
 
@@ -43,6 +47,7 @@ def _build(tmp_path, name, src_text):
     lib.orc_fft3d.argtypes = [i64, i64, i64, i32, dp]
     lib.orc_evolve.argtypes = [i64, i64, i64, dp, ctypes.c_double, ctypes.c_double]
     lib.orc_checksum.argtypes = [i64, i64, i64, dp, dp]
+    lib.orc_lu.argtypes = [i64, i64, dp, ctypes.POINTER(ctypes.c_int32)]
     return lib
 
 
@@ -90,6 +95,22 @@ def _pins_pass(lib) -> bool:
     flat = g.reshape(-1)
     want = sum(flat[17 * j] for j in range(1024))
     ok &= bool(abs(complex(out[0], out[1]) - want) < 1e-12)
+    # 4. LU with partial pivoting: reconstruction P A = L U, and the first
+    # largest pivot on a matrix with ties in magnitude
+    rng = np.random.default_rng(4)
+    for a0 in (rng.uniform(-1, 1, (9, 9)), np.array([[1.0, 2.0], [-1.0, 3.0]])):
+        n = a0.shape[0]
+        m = np.ascontiguousarray(a0.copy())
+        piv = np.zeros(n, dtype=np.int32)
+        lib.orc_lu(n, n, _dp(m), piv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        L = np.tril(m, -1) + np.eye(n)
+        U = np.triu(m)
+        perm = np.arange(n)
+        for j, p in enumerate(piv):
+            perm[[j, p]] = perm[[p, j]]
+        ok &= bool(np.linalg.norm(a0[perm] - L @ U) < 1e-14 * n * np.linalg.norm(a0))
+        if n == 2:
+            ok &= bool(list(piv) == [0, 1])   # |1| == |-1|: the first row stays
     return ok
 
 
