@@ -328,6 +328,39 @@ def paper_2d_section(torch, fb, reps: int = 10) -> dict:
     return out
 
 
+LU_N = 2048
+
+
+def lu_section(torch, fb, reps: int = 10) -> dict:
+    """The paper's other function block at its size (section 5.1(b)): LU
+    with partial pivoting of a 2048 x 2048 binary64 matrix (entries uniform
+    on [-1, 1), SplitMix64 seed 9), in place on the device; each repetition
+    factors a fresh copy (the copy is outside the timed interval)."""
+    from paper_2004_09883_amd import inputs
+
+    n = LU_N
+    a0 = torch.from_numpy(inputs.uniform_grid((1, n, n), 9).real.reshape(n, n).copy()).cuda()
+    a = torch.empty_like(a0)
+    ipiv = torch.empty(n, dtype=torch.int32, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for r in range(reps + 2):
+        a.copy_(a0)
+        s.record()
+        fb.fb_lu_factor(a, ipiv, info)
+        e.record()
+        torch.cuda.synchronize()
+        if r >= 2:
+            times.append(s.elapsed_time(e))
+    ms = sorted(times)[len(times) // 2]
+    flops = 2.0 * n ** 3 / 3.0
+    return {"workload": "LU with partial pivoting, %dx%d binary64, uniform [-1,1) (seed 9)" % (n, n),
+            "ms_median": round(ms, 4), "ms_min": round(min(times), 4), "gflops": round(flops / ms / 1e6, 1),
+            "fp64_peak_frac": round(flops / (ms * 1e-3) / 78.6e12, 4), "info": int(info.cpu()[0]),
+            "launches": 1 + 4 * ((n + 15) // 16)}
+
+
 def copy_reference(torch, nbytes: int = 1 << 29, reps: int = 20) -> dict:
     """A plain device-to-device copy (torch's copy kernel) of a grid-sized
     buffer: the practical bandwidth ceiling a streaming pass is compared with."""
@@ -530,6 +563,7 @@ def main() -> int:
         rec["forms_512x256x256"] = forms_section(torch, fb)
         rec["batched"] = batched_section(torch, fb)
         rec["paper_2d_2048"] = paper_2d_section(torch, fb)
+        rec["lu_2048"] = lu_section(torch, fb)
         rec["copy_reference"] = copy_reference(torch)
     if args.serve_seconds > 0:
         from paper_2004_09883_amd import serve
@@ -557,6 +591,16 @@ def main() -> int:
             p2["cpu_oracle_threads"] = oracle.threads()
             for k in ("c128", "c64"):
                 p2[k]["x_vs_cpu_with_copies"] = round(cpu_ms / p2[k]["with_copies_ms"], 1)
+        if "lu_2048" in rec:
+            import oracle
+            from paper_2004_09883_amd import inputs
+            a = inputs.uniform_grid((1, LU_N, LU_N), 9).real.reshape(LU_N, LU_N).copy()
+            t0 = time.perf_counter()
+            oracle.lu(a)
+            cpu_ms = (time.perf_counter() - t0) * 1e3
+            rec["lu_2048"]["cpu_oracle_ms"] = round(cpu_ms, 1)
+            rec["lu_2048"]["cpu_oracle_threads"] = oracle.threads()
+            rec["lu_2048"]["x_vs_cpu"] = round(cpu_ms / rec["lu_2048"]["ms_median"], 1)
     print(json.dumps(rec), flush=True)
     return 0
 

@@ -165,6 +165,22 @@ fb_status fb_fill_uniform(const fb_plan *p, void *x, uint64_t seed, void *hip_st
  * Errors as fb_fft3d_exec. */
 fb_status fb_fft3d_forward_uniform(const fb_plan *p, uint64_t seed, void *out, void *hip_stream);
 
+/* ---- LU function block -------------------------------------------------
+ * The paper's other offloaded function block (section 5.1(b): an LU
+ * factorization replaced by a GPU library call of the same meaning).
+ * LU factorization with partial pivoting of the row-major n x n binary64
+ * matrix a (device memory, row stride lda >= n), in place: on return the
+ * strictly lower part holds L (unit diagonal, not stored) and the upper part
+ * U, with P a = L U where P applies, for j = 0..n-1 in order, the swap of
+ * rows j and ipiv[j] (0-based, ipiv[j] >= j).  The pivot of column j is the
+ * first row of largest magnitude.  info (device) receives 0, or j + 1 for
+ * the first column j whose pivot is zero (the factorization still
+ * completes, as the usual library convention).  ipiv (n int32) and info are
+ * device memory owned by the caller; nothing is allocated.  1 <= n <= 2048
+ * (else FB_ERR_UNSUPPORTED_SIZE); NULL or misaligned pointers, lda < n or
+ * overlapping arguments -> FB_ERR_INVALID_ARG.  Stream-ordered. */
+fb_status fb_lu_factor(double *a, int64_t n, int64_t lda, int32_t *ipiv, int32_t *info, void *hip_stream);
+
 /* ---- Batched form ------------------------------------------------------
  * Many independent complex64 transforms in one call: n1d 1D transforms of
  * lengths lens[0..n1d) (each 2^a or 3*2^a, 2 <= n <= 2^21) and n2d 2D

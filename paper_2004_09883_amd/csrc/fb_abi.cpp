@@ -19,6 +19,7 @@
 
 #include "fb.h"
 #include "fb_internal.hpp"
+#include "fb_lu.hpp"
 
 using fb::PassArgs;
 using fb::PassInfo;
@@ -483,6 +484,34 @@ fb_status fb_fft3d_exec(const fb_plan *p, const void *in, void *out, int dir, vo
     if (check_no_partial_overlap(p, in, out, true, "fb_fft3d_exec")) return (fb_status)g_code;
     if (check_device(p)) return (fb_status)g_code;
     if (run_passes(p, in, out, dir, nullptr, (hipStream_t)hip_stream)) return (fb_status)g_code;
+    return (fb_status)ok();
+}
+
+fb_status fb_lu_factor(double *a, int64_t n, int64_t lda, int32_t *ipiv, int32_t *info, void *hip_stream)
+{
+    if (n < 1 || n > fb::LU_MAX_N)
+        return (fb_status)fail(FB_ERR_UNSUPPORTED_SIZE, "n must be in 1..%lld, got %lld", (long long)fb::LU_MAX_N,
+                               (long long)n);
+    if (lda < n) return (fb_status)fail(FB_ERR_INVALID_ARG, "lda (%lld) < n (%lld)", (long long)lda, (long long)n);
+    if (!a || (uintptr_t)a % 8) return (fb_status)fail(FB_ERR_INVALID_ARG, "a is NULL or not 8-byte aligned");
+    if (!ipiv || (uintptr_t)ipiv % 4 || !info || (uintptr_t)info % 4)
+        return (fb_status)fail(FB_ERR_INVALID_ARG, "ipiv / info is NULL or not 4-byte aligned");
+    {
+        // ipiv and info must not overlap the matrix
+        const uintptr_t a0 = (uintptr_t)a, a1 = a0 + (uintptr_t)((n - 1) * lda + n) * 8;
+        const uintptr_t p0 = (uintptr_t)ipiv, p1 = p0 + (uintptr_t)n * 4, i0 = (uintptr_t)info, i1 = i0 + 4;
+        if ((p0 < a1 && a0 < p1) || (i0 < a1 && a0 < i1) || (i0 < p1 && p0 < i1))
+            return (fb_status)fail(FB_ERR_INVALID_ARG, "a, ipiv and info must not overlap");
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    // model bytes: the trailing updates read and write A22 once per panel
+    double bytes = 0.0;
+    for (int64_t k = 0; k < n; k += fb::LU_NB) {
+        const double r = (double)(n - k);
+        bytes += 16.0 * r * r;
+    }
+    hipError_t e = timed_launch("lu<f64>", bytes, st, [&] { return fb::launch_lu(a, n, lda, ipiv, info, st); });
+    if (e != hipSuccess) return (fb_status)hip_fail(e, "lu launch");
     return (fb_status)ok();
 }
 

@@ -31,7 +31,7 @@ DTYPE_NAMES = {FB_C128: "c128", FB_C64: "c64", FB_C64_SPLITBF16: "c64_splitbf16"
 # every entry point declared in include/fb.h
 EXPORTS = ("fb_version", "fb_last_error", "fb_describe_shape", "fb_fft3d_plan", "fb_fft3d_destroy",
            "fb_plan_device_bytes", "fb_plan_describe", "fb_fft3d_exec", "fb_spectral_evolve",
-           "fb_checksum", "fb_spectral_step", "fb_spectral_steps", "fb_fft3d_exec_host", "fb_fill_uniform", "fb_fft3d_forward_uniform", "fb_fft3d_exec_axes",
+           "fb_checksum", "fb_spectral_step", "fb_spectral_steps", "fb_fft3d_exec_host", "fb_lu_factor", "fb_fill_uniform", "fb_fft3d_forward_uniform", "fb_fft3d_exec_axes",
            "fb_profile_enable", "fb_profile_report", "fb_batch_plan", "fb_batch_destroy", "fb_batch_elements",
            "fb_batch_offsets", "fb_batch_workspace_bytes", "fb_batch_launches", "fb_batch_describe",
            "fb_batch_exec", "fb_server_create", "fb_server_submit", "fb_server_poll",
@@ -94,6 +94,7 @@ def load():
         "fb_spectral_step": (i32, [vp, vp, vp, dbl, dbl, vp, vp]),
         "fb_fill_uniform": (i32, [vp, vp, ctypes.c_uint64, vp]),
         "fb_fft3d_exec_host": (i32, [vp, vp, vp, i32]),
+        "fb_lu_factor": (i32, [vp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp]),
         "fb_spectral_steps": (i32, [vp, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double), i32, vp, vp]),
         "fb_fft3d_forward_uniform": (i32, [vp, ctypes.c_uint64, vp, vp]),
         "fb_fft3d_exec_axes": (i32, [vp, vp, vp, i32, i32, vp]),
@@ -263,6 +264,25 @@ def fb_spectral_step(plan: Plan, uhat0, x_out, alpha: float, t: float, out2=None
     plan.check_tensor(x_out, "x_out")
     _check(load().fb_spectral_step(plan.handle, _ptr(uhat0), _ptr(x_out), float(alpha), float(t),
                                    _ptr(out2), _stream(stream)))
+
+
+def fb_lu_factor(a, ipiv, info, stream=None):
+    """a: square float64 device tensor (row-major, factored in place); ipiv:
+    int32 device tensor of n elements; info: int32 device tensor of at least
+    one element."""
+    import torch
+    if not isinstance(a, int):
+        if a.dim() != 2 or a.shape[0] != a.shape[1] or a.dtype != torch.float64 or not a.is_cuda:
+            raise FbError(FB_ERR_INVALID_ARG, "a must be a square float64 device tensor")
+        if a.stride(1) != 1:
+            raise FbError(FB_ERR_INVALID_ARG, "a must have unit column stride (row-major)")
+        n, lda = a.shape[0], a.stride(0)
+    else:
+        raise FbError(FB_ERR_INVALID_ARG, "pass a tensor")
+    for t, name, need in ((ipiv, "ipiv", n), (info, "info", 1)):
+        if t.dtype != torch.int32 or not t.is_cuda or t.numel() < need or not t.is_contiguous():
+            raise FbError(FB_ERR_INVALID_ARG, f"{name} must be a contiguous int32 device tensor of >= {need} elements")
+    _check(load().fb_lu_factor(_ptr(a), n, lda, _ptr(ipiv), _ptr(info), _stream(stream)))
 
 
 def fb_fft3d_exec_host(plan: Plan, x_in, x_out, direction: int = FB_FORWARD):

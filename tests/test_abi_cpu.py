@@ -105,3 +105,19 @@ def test_batch_plan_rejects_before_device():
     assert lib.fb_batch_exec(None, 16, 16, 256, 1 << 20, -1, 1, None) == fb.FB_ERR_INVALID_ARG
     assert lib.fb_batch_elements(None) == 0
     lib.fb_batch_destroy(None)
+
+
+def test_lu_and_steps_reject_before_device():
+    """Argument checks of the LU block and the multi-step call run before any
+    HIP call (no device here)."""
+    lib = fb.load()
+    assert lib.fb_lu_factor(16, 0, 0, 32, 64, None) == fb.FB_ERR_UNSUPPORTED_SIZE
+    assert lib.fb_lu_factor(16, 4096, 4096, 32, 64, None) == fb.FB_ERR_UNSUPPORTED_SIZE
+    assert lib.fb_lu_factor(16, 8, 4, 32 << 10, 64 << 10, None) == fb.FB_ERR_INVALID_ARG    # lda < n
+    assert lib.fb_lu_factor(None, 8, 8, 32 << 10, 64 << 10, None) == fb.FB_ERR_INVALID_ARG
+    assert lib.fb_lu_factor(12, 8, 8, 32 << 10, 64 << 10, None) == fb.FB_ERR_INVALID_ARG   # misaligned
+    assert lib.fb_lu_factor(1 << 20, 8, 8, (1 << 20) + 64, 64 << 20, None) == fb.FB_ERR_INVALID_ARG  # overlap
+    ts = (ctypes.c_double * 2)(1.0, 2.0)
+    assert lib.fb_spectral_steps(None, 16, 16, 1e-6, ts, 2, None, None) == fb.FB_ERR_INVALID_ARG
+    assert lib.fb_fft3d_exec_host(None, 16, 16, -1) == fb.FB_ERR_INVALID_ARG
+    assert lib.fb_fft3d_forward_uniform(None, 1, 16, None) == fb.FB_ERR_INVALID_ARG
