@@ -401,6 +401,7 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the cache-flushed and fused-steps timings of the block (profiling runs: only the "
                          "timed block's kernels are launched)")
+    ap.add_argument("--lu-only", action="store_true", help="only run the LU section (for kernel traces)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the batched-form section (for kernel traces)")
     ap.add_argument("--copy-only", action="store_true",
@@ -425,6 +426,9 @@ def main() -> int:
         return 0
     if args.forms_only:
         print(json.dumps({"forms_512x256x256": forms_section(torch, fb, reps=10)}), flush=True)
+        return 0
+    if args.lu_only:
+        print(json.dumps({"lu_2048": lu_section(torch, fb)}), flush=True)
         return 0
     if args.batched_only:
         print(json.dumps({"batched": batched_section(torch, fb)}), flush=True)

@@ -8,10 +8,9 @@
 //             scaling, rank-1 update of the panel's remaining columns); one
 //             workgroup holds the whole panel in registers, two rows per
 //             thread, so n <= 2 * 1024;
-//   lu_swap   applies the panel's row swaps, in order, to every column
-//             outside the panel (one thread per column);
-//   lu_trsm   U12 = L11^-1 A12 for the columns right of the panel (one
-//             thread per column, L11 in LDS);
+//   lu_swap_trsm  applies the panel's row swaps, in order, to every column
+//             outside the panel, then U12 = L11^-1 A12 for the columns right
+//             of it (one thread per column, L11 in LDS);
 //   lu_gemm   A22 -= L21 U12 on 64 x 64 tiles (L21 and U12 tiles in LDS).
 // Every element receives its updates in increasing column order j, as in
 // unblocked elimination.  On gfx950 the dense binary64 matrix-core rate
@@ -19,6 +18,7 @@
 // so the update uses vector FMAs.
 #include <hip/hip_runtime.h>
 
+#include "fb_device.hpp"
 #include "fb_lu.hpp"
 
 namespace fb {
@@ -35,12 +35,19 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
     lu_panel(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb, int32_t *__restrict__ ipiv,
              int32_t *__restrict__ info)
 {
-    __shared__ double rowj[LU_NB], rowp[LU_NB];
-    __shared__ double wbest[LU_PANEL_THREADS / 64];
-    __shared__ int widx[LU_PANEL_THREADS / 64];
-    __shared__ int s_p;
+    constexpr int W = LU_PANEL_THREADS / 64;   // waves
+    // double-buffered by column parity: column j + 1 writes the other half, so
+    // the only barriers of a column are after the wave maxima and after the
+    // row exchange (a thread reaching column j + 1's first barrier has
+    // finished every read of column j - 1's buffers)
+    __shared__ double rowj[2][LU_NB], rowp[2][LU_NB];
+    __shared__ double wbest[2][W];
+    __shared__ int widx[2][W];
     const int tid = threadIdx.x;
     const int m = (int)(n - k);   // rows of the panel (<= LU_ROWS * LU_PANEL_THREADS, checked on the host)
+    // thread 0 keeps the first zero pivot in a register (a global read per
+    // column would stall every column's barrier on memory latency)
+    int32_t zero_at = tid == 0 ? info[0] : 0;
     double v[LU_ROWS][LU_NB];
 #pragma unroll
     for (int r = 0; r < LU_ROWS; r++) {
@@ -50,9 +57,12 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
             v[r][c] = (i < m && c < nb) ? a[(k + i) * lda + k + c] : 0.0;
     }
 
-#pragma unroll
-    for (int j = 0; j < LU_NB; j++) {
+    // columns as a compile-time sequence, so that every index into v is a
+    // constant and v stays in registers
+    static_for<0, LU_NB>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
         if (j < nb) {   // uniform
+            constexpr int h = j & 1;
             // ---- pivot: the first row i >= j of largest |a[i][j]|
             double best = -1.0;
             int bi = 0x7fffffff;
@@ -77,35 +87,37 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
                 }
             }
             if ((tid & 63) == 0) {
-                wbest[tid >> 6] = best;
-                widx[tid >> 6] = bi;
+                wbest[h][tid >> 6] = best;
+                widx[h][tid >> 6] = bi;
             }
             __syncthreads();
+            // every thread reduces the W wave maxima itself (broadcast reads)
+            double b = wbest[h][0];
+            int p = widx[h][0];
+#pragma unroll
+            for (int w = 1; w < W; w++) {
+                const double wb = wbest[h][w];
+                const int wi = widx[h][w];
+                if (wb > b || (wb == b && wi < p)) {
+                    b = wb;
+                    p = wi;
+                }
+            }
             if (tid == 0) {
-                double b = wbest[0];
-                int p = widx[0];
-                for (int w = 1; w < LU_PANEL_THREADS / 64; w++)
-                    if (wbest[w] > b || (wbest[w] == b && widx[w] < p)) {
-                        b = wbest[w];
-                        p = widx[w];
-                    }
-                s_p = p;
                 ipiv[k + j] = (int32_t)(k + p);
-                if (b == 0.0 && info[0] == 0) info[0] = (int32_t)(k + j + 1);
+                if (b == 0.0 && zero_at == 0) zero_at = (int32_t)(k + j + 1);
             }
-            __syncthreads();
-            const int p = s_p;
-            // ---- swap rows j and p of the panel; rowp becomes the pivot row
+            // ---- exchange rows j and p of the panel through LDS; rowp is the pivot row
 #pragma unroll
             for (int r = 0; r < LU_ROWS; r++) {
                 const int i = tid + LU_PANEL_THREADS * r;
                 if (i == p) {
 #pragma unroll
-                    for (int c = 0; c < LU_NB; c++) rowp[c] = v[r][c];
+                    for (int c = 0; c < LU_NB; c++) rowp[h][c] = v[r][c];
                 }
                 if (i == j) {
 #pragma unroll
-                    for (int c = 0; c < LU_NB; c++) rowj[c] = v[r][c];
+                    for (int c = 0; c < LU_NB; c++) rowj[h][c] = v[r][c];
                 }
             }
             __syncthreads();
@@ -114,14 +126,14 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
                 const int i = tid + LU_PANEL_THREADS * r;
                 if (i == j) {
 #pragma unroll
-                    for (int c = 0; c < LU_NB; c++) v[r][c] = rowp[c];
+                    for (int c = 0; c < LU_NB; c++) v[r][c] = rowp[h][c];
                 } else if (i == p) {
 #pragma unroll
-                    for (int c = 0; c < LU_NB; c++) v[r][c] = rowj[c];
+                    for (int c = 0; c < LU_NB; c++) v[r][c] = rowj[h][c];
                 }
             }
             // ---- scale the column below the pivot, update the panel's right part
-            const double piv = rowp[j];
+            const double piv = rowp[h][j];
             if (piv != 0.0) {
 #pragma unroll
                 for (int r = 0; r < LU_ROWS; r++) {
@@ -130,13 +142,12 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
                         const double l = v[r][j] / piv;
                         v[r][j] = l;
 #pragma unroll
-                        for (int c = j + 1; c < LU_NB; c++) v[r][c] -= l * rowp[c];
+                        for (int c = j + 1; c < LU_NB; c++) v[r][c] -= l * rowp[h][c];
                     }
                 }
             }
-            __syncthreads();   // rowp / rowj are rewritten by the next column
         }
-    }
+    });
 
 #pragma unroll
     for (int r = 0; r < LU_ROWS; r++) {
@@ -147,48 +158,70 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
                 if (c < nb) a[(k + i) * lda + k + c] = v[r][c];
         }
     }
+    if (tid == 0) info[0] = zero_at;
 }
 
 // The panel's swaps (rows k+j <-> ipiv[k+j], j = 0..nb-1 in order) on every
-// column outside the panel.
-__global__ void __launch_bounds__(256)
-    lu_swap(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb, const int32_t *__restrict__ ipiv)
-{
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= n || (c >= k && c < k + nb)) return;
-    for (int j = 0; j < nb; j++) {
-        const int64_t p = ipiv[k + j];
-        if (p != k + j) {
-            const double t = a[(k + j) * lda + c];
-            a[(k + j) * lda + c] = a[p * lda + c];
-            a[p * lda + c] = t;
-        }
-    }
-}
-
-// U12 = L11^-1 A12: columns c >= k + nb of rows k .. k+nb-1.
-__global__ void __launch_bounds__(256)
-    lu_trsm(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb)
+// column outside the panel, then U12 = L11^-1 A12 on the columns right of
+// it.  The swaps are first composed into one permutation of the at most
+// 2 nb rows they touch (each workgroup does it in LDS from ipiv), so that a
+// column loads every touched row at once and stores each once, instead of
+// nb dependent swaps.  One thread per column: row accesses are coalesced.
+constexpr int LU_SWAP_THREADS = 64;
+__global__ void __launch_bounds__(LU_SWAP_THREADS)
+    lu_swap_trsm(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb, const int32_t *__restrict__ ipiv)
 {
     __shared__ double L[LU_NB][LU_NB + 1];
-    for (int idx = threadIdx.x; idx < LU_NB * LU_NB; idx += 256) {
+    __shared__ int64_t dst[2 * LU_NB], src[2 * LU_NB];
+    __shared__ int npair;
+    __shared__ int64_t piv[LU_NB];
+    if (threadIdx.x < LU_NB) piv[threadIdx.x] = threadIdx.x < nb ? ipiv[k + threadIdx.x] : 0;
+    for (int idx = threadIdx.x; idx < LU_NB * LU_NB; idx += LU_SWAP_THREADS) {
         const int i = idx / LU_NB, j = idx % LU_NB;
         L[i][j] = (i < nb && j < nb) ? a[(k + i) * lda + k + j] : 0.0;
     }
     __syncthreads();
-    const int64_t c = k + nb + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= n) return;
-    double x[LU_NB];
+    if (threadIdx.x == 0) {
+        // touched rows (dst): k .. k+nb-1 first (entries 0 .. nb-1), then
+        // the pivot rows below the block; src[q] = the original row whose
+        // content row dst[q] holds after the swaps so far
+        int cnt = nb;
+        for (int j = 0; j < nb; j++) dst[j] = src[j] = k + j;
+        for (int j = 0; j < nb; j++) {
+            const int64_t pr = piv[j];
+            int q = pr - k < nb ? (int)(pr - k) : -1;   // pivot rows are >= k + j
+            if (q < 0) {
+                for (int e = nb; e < cnt; e++)
+                    if (dst[e] == pr) q = e;
+                if (q < 0) {
+                    q = cnt++;
+                    dst[q] = src[q] = pr;
+                }
+            }
+            const int64_t t = src[j];
+            src[j] = src[q];
+            src[q] = t;
+        }
+        npair = cnt;
+    }
+    __syncthreads();
+    const int64_t c = (int64_t)blockIdx.x * LU_SWAP_THREADS + threadIdx.x;
+    if (c >= n || (c >= k && c < k + nb)) return;
+    const int np = npair;
+    double val[2 * LU_NB];
 #pragma unroll
-    for (int i = 0; i < LU_NB; i++) x[i] = i < nb ? a[(k + i) * lda + c] : 0.0;
+    for (int q = 0; q < 2 * LU_NB; q++) val[q] = q < np ? a[src[q] * lda + c] : 0.0;
+    const bool right = c >= k + nb;
+    if (right) {
+        static_for<1, LU_NB>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
 #pragma unroll
-    for (int i = 1; i < LU_NB; i++) {
-#pragma unroll
-        for (int j = 0; j < i; j++) x[i] -= L[i][j] * x[j];
+            for (int j = 0; j < i; j++) val[i] -= L[i][j] * val[j];
+        });
     }
 #pragma unroll
-    for (int i = 1; i < LU_NB; i++)
-        if (i < nb) a[(k + i) * lda + c] = x[i];
+    for (int q = 0; q < 2 * LU_NB; q++)
+        if (q < np && (dst[q] != src[q] || (right && q < nb))) a[dst[q] * lda + c] = val[q];
 }
 
 // A22 -= L21 U12 on 64 x 64 tiles: rows and columns >= k + nb.
@@ -252,10 +285,11 @@ hipError_t launch_lu(double *a, int64_t n, int64_t lda, int32_t *ipiv, int32_t *
     for (int64_t k = 0; e == hipSuccess && k < n; k += LU_NB) {
         const int nb = (int)(n - k < LU_NB ? n - k : LU_NB);
         hipLaunchKernelGGL(lu_panel, dim3(1), dim3(LU_PANEL_THREADS), 0, st, a, n, lda, k, nb, ipiv, info);
-        hipLaunchKernelGGL(lu_swap, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, n, lda, k, nb, ipiv);
+        if (n > nb)
+            hipLaunchKernelGGL(lu_swap_trsm, dim3((unsigned)((n + LU_SWAP_THREADS - 1) / LU_SWAP_THREADS)),
+                               dim3(LU_SWAP_THREADS), 0, st, a, n, lda, k, nb, ipiv);
         const int64_t rest = n - k - nb;
         if (rest > 0) {
-            hipLaunchKernelGGL(lu_trsm, dim3((unsigned)((rest + 255) / 256)), dim3(256), 0, st, a, n, lda, k, nb);
             const unsigned t = (unsigned)((rest + LU_TILE - 1) / LU_TILE);
             hipLaunchKernelGGL(lu_gemm, dim3(t, t), dim3(256), 0, st, a, n, lda, k, nb);
         }
