@@ -966,7 +966,7 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
             if (it != roots.end()) rt = it->second;
             else {
                 rt = dev_alloc<float2>(b, L, e);
-                if (e == hipSuccess) e = fb::launch_roots(L, nullptr, rt, nullptr);
+                if (e == hipSuccess) e = fb::launch_pretwiddle(n1, n2, rt, nullptr);
                 roots[L] = rt;
             }
             g2.args.ptw = rt;
@@ -977,9 +977,10 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
             g2.inv_scale = 1.0 / (double)L;
             const int P2 = fb::find_pass_pair((int)n2).pencils_per_wg;
             g2.ntiles = (cnt * n1 + P2 - 1) / P2;
-            // the pass-2 kernel indexes the root table by q b < n2 n1 without a reduction
+            // the pass-2 kernel reads the pre-twiddle table at the element's offset
+            // within its transform (< n2 n1)
             if (!group_in_bounds(g1, segmax, b->total) || !group_in_bounds(g2, segmax, b->total) ||
-                g2.args.ptw_len < n2 * g2.args.seg_pencils)
+                g2.args.ptw_len < n2 * n1)
                 e = hipErrorInvalidValue;
             g2.phase = 1;
             pass1.push_back(g1);

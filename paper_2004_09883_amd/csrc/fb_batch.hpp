@@ -40,5 +40,8 @@ hipError_t launch_batch_persistent(const BatchGroup *groups_dev, int g0, int g1,
 
 // tables[m] = w_n^m = exp(-2 pi i m / n), m < n, binary64 and binary32
 hipError_t launch_roots(int64_t n, double2 *t64, float2 *t32, hipStream_t st);
+// t32[q n1 + b] = w_(n1 n2)^(q b): the second-pass pre-twiddles of a two-pass
+// transform, laid out like its data
+hipError_t launch_pretwiddle(int64_t n1, int64_t n2, float2 *t32, hipStream_t st);
 
 }  // namespace fb

@@ -25,9 +25,9 @@ struct PassArgs {
     // the geometry above then applies to the local pencil p % seg_pencils
     const int64_t *seg_off;
     int64_t seg_pencils;
-    // pre-twiddle on load (two-pass long transforms): element q of local
-    // pencil b is multiplied by ptw[q b], ptw[m] = w_L^m; requires
-    // ptw_len >= N seg_pencils so that q b never leaves the table
+    // pre-twiddle on load (two-pass long transforms): the element at offset
+    // o from the start of its segment is multiplied by ptw[o] (a table laid
+    // out like one segment); requires ptw_len >= the segment's extent
     const void *ptw;
     int64_t ptw_len;
     // pencil-pair passes: distance in elements between the outputs of the two

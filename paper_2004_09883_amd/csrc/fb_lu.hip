@@ -6,8 +6,8 @@
 //   lu_panel  factors rows k..n-1 of the panel column by column (pivot =
 //             first row of largest magnitude, row swap inside the panel,
 //             scaling, rank-1 update of the panel's remaining columns); one
-//             workgroup holds the whole panel in registers, two rows per
-//             thread, so n <= 2 * 1024;
+//             workgroup holds the whole panel in registers, four rows per
+//             thread of 512, so n <= 2048;
 //   lu_swap_trsm  applies the panel's row swaps, in order, to every column
 //             outside the panel, then U12 = L11^-1 A12 for the columns right
 //             of it (one thread per column, L11 in LDS);
@@ -23,8 +23,9 @@
 
 namespace fb {
 
-constexpr int LU_PANEL_THREADS = 1024;
-constexpr int LU_ROWS = 2;   // rows of the panel per thread
+constexpr int LU_PANEL_THREADS = 512;
+constexpr int LU_ROWS = 4;   // rows of the panel per thread
+static_assert(LU_ROWS * LU_PANEL_THREADS >= LU_MAX_N, "the panel kernel holds every row of a panel");
 
 __global__ void lu_init(int32_t *info)
 {
@@ -77,31 +78,46 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
                     }
                 }
             }
+            {
+                // the wave's largest magnitude, then the smallest row holding it
+                double wm = best;
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_xor(best, off);
-                const int oi = __shfl_xor(bi, off);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
-                }
+                for (int off = 32; off > 0; off >>= 1) wm = fmax(wm, __shfl_xor(wm, off));
+                int cand = best == wm ? bi : 0x7fffffff;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) cand = min(cand, __shfl_xor(cand, off));
+                best = wm;
+                bi = cand;
             }
             if ((tid & 63) == 0) {
                 wbest[h][tid >> 6] = best;
                 widx[h][tid >> 6] = bi;
             }
             __syncthreads();
-            // every thread reduces the W wave maxima itself (broadcast reads)
-            double b = wbest[h][0];
-            int p = widx[h][0];
-#pragma unroll
-            for (int w = 1; w < W; w++) {
-                const double wb = wbest[h][w];
-                const int wi = widx[h][w];
-                if (wb > b || (wb == b && wi < p)) {
-                    b = wb;
-                    p = wi;
+            // every wave reduces the W wave maxima: lane l < W takes entry l,
+            // then shuffle trees over W lanes; lane 0's result is made
+            // wave-uniform
+            double b = -1.0;
+            int p = 0x7fffffff;
+            {
+                const int lane = tid & 63;
+                if (lane < W) {
+                    b = wbest[h][lane];
+                    p = widx[h][lane];
                 }
+                double wm = b;
+#pragma unroll
+                for (int off = W / 2; off > 0; off >>= 1) wm = fmax(wm, __shfl_xor(wm, off));
+                int cand = b == wm ? p : 0x7fffffff;
+#pragma unroll
+                for (int off = W / 2; off > 0; off >>= 1) cand = min(cand, __shfl_xor(cand, off));
+                b = wm;
+                p = cand;
+                p = __builtin_amdgcn_readfirstlane(p);
+                const unsigned long long bb = (unsigned long long)__double_as_longlong(b);
+                const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)bb);
+                const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(bb >> 32));
+                b = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
             }
             if (tid == 0) {
                 ipiv[k + j] = (int32_t)(k + p);
@@ -174,35 +190,44 @@ __global__ void __launch_bounds__(LU_SWAP_THREADS)
     __shared__ double L[LU_NB][LU_NB + 1];
     __shared__ int64_t dst[2 * LU_NB], src[2 * LU_NB];
     __shared__ int npair;
-    __shared__ int64_t piv[LU_NB];
-    if (threadIdx.x < LU_NB) piv[threadIdx.x] = threadIdx.x < nb ? ipiv[k + threadIdx.x] : 0;
     for (int idx = threadIdx.x; idx < LU_NB * LU_NB; idx += LU_SWAP_THREADS) {
         const int i = idx / LU_NB, j = idx % LU_NB;
         L[i][j] = (i < nb && j < nb) ? a[(k + i) * lda + k + j] : 0.0;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // touched rows (dst): k .. k+nb-1 first (entries 0 .. nb-1), then
-        // the pivot rows below the block; src[q] = the original row whose
-        // content row dst[q] holds after the swaps so far
+    {
+        // The workgroup is one wave.  Lane q holds touched row dst[q] and the
+        // original row src[q] whose content it holds after the swaps so far:
+        // rows k .. k+nb-1 in lanes 0 .. nb-1, pivot rows below the block
+        // appended as they first appear.
+        static_assert(LU_SWAP_THREADS == 64 && 2 * LU_NB <= 64, "one wave composes the permutation");
+        const int lane = threadIdx.x;
+        const int64_t pv = lane < nb ? (int64_t)ipiv[k + lane] : 0;
+        int64_t d = lane < nb ? k + lane : -1;
+        int64_t sr = d;
         int cnt = nb;
-        for (int j = 0; j < nb; j++) dst[j] = src[j] = k + j;
         for (int j = 0; j < nb; j++) {
-            const int64_t pr = piv[j];
-            int q = pr - k < nb ? (int)(pr - k) : -1;   // pivot rows are >= k + j
-            if (q < 0) {
-                for (int e = nb; e < cnt; e++)
-                    if (dst[e] == pr) q = e;
-                if (q < 0) {
+            const int64_t pr = __shfl(pv, j);
+            int q;
+            if (pr - k < nb) {
+                q = (int)(pr - k);   // inside the block (pivot rows are >= k + j)
+            } else {
+                const unsigned long long hit = __ballot(lane >= nb && lane < cnt && d == pr);
+                if (hit) {
+                    q = __ffsll((long long)hit) - 1;
+                } else {
                     q = cnt++;
-                    dst[q] = src[q] = pr;
+                    if (lane == q) d = sr = pr;
                 }
             }
-            const int64_t t = src[j];
-            src[j] = src[q];
-            src[q] = t;
+            const int64_t sj = __shfl(sr, j), sq = __shfl(sr, q);
+            if (lane == j) sr = sq;
+            if (lane == q) sr = sj;
         }
-        npair = cnt;
+        if (lane < cnt) {
+            dst[lane] = d;
+            src[lane] = sr;
+        }
+        if (lane == 0) npair = cnt;
     }
     __syncthreads();
     const int64_t c = (int64_t)blockIdx.x * LU_SWAP_THREADS + threadIdx.x;

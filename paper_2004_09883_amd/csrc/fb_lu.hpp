@@ -6,7 +6,7 @@
 namespace fb {
 
 constexpr int LU_NB = 16;            // panel width (columns factored per panel)
-constexpr int64_t LU_MAX_N = 2048;   // the panel kernel holds 2 rows per thread of one 1024-thread workgroup
+constexpr int64_t LU_MAX_N = 2048;   // the panel kernel holds 4 rows per thread of one 512-thread workgroup
 
 // Blocked LU with partial pivoting of the row-major n x n matrix a (row
 // stride lda) in place; ipiv[j] = row swapped with row j at step j; info[0]

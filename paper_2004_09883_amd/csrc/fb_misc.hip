@@ -84,6 +84,26 @@ __global__ void roots_kernel(int64_t n, double2 *t64, float2 *t32)
     t32[m] = make_float2((float)w.x, (float)w.y);
 }
 
+// Pre-twiddle table of a two-pass transform of length n = n1 n2, laid out
+// like the data the second pass reads: t32[q n1 + b] = w_n^(q b), b < n1,
+// q < n2 (q b < n, so no reduction is needed).
+__global__ void pretwiddle_kernel(int64_t n1, int64_t n2, float2 *t32)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n1 * n2) return;
+    const int64_t q = m / n1, b = m % n1;
+    const double2 w = root_of_unity(q * b, n1 * n2);
+    t32[m] = make_float2((float)w.x, (float)w.y);
+}
+
+hipError_t launch_pretwiddle(int64_t n1, int64_t n2, float2 *t32, hipStream_t st)
+{
+    const int threads = 256;
+    const int64_t blocks = (n1 * n2 + threads - 1) / threads;
+    hipLaunchKernelGGL(pretwiddle_kernel, dim3((unsigned)blocks), dim3(threads), 0, st, n1, n2, t32);
+    return hipGetLastError();
+}
+
 hipError_t launch_roots(int64_t n, double2 *t64, float2 *t32, hipStream_t st)
 {
     const int threads = 256;

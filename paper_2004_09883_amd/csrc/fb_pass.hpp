@@ -116,20 +116,20 @@ template <typename V> __device__ __forceinline__ void st_v(elem_t<V> *p, V v)
     }
 }
 
-// Pre-twiddle of element e of local pencil lp (and lp + 1 for a pair):
-// the factor is ptw[e lp].  The product stays below the table length without
-// a reduction because e < N and lp < seg_pencils, and the table holds
-// N seg_pencils roots (checked on the host), so 32-bit arithmetic suffices.
-template <typename V> __device__ __forceinline__ V pre_twiddle(V v, int e, int lp, const void *ptw)
+// Pre-twiddle of the element at offset o from the start of its segment
+// (and of the pair's second pencil, `istep` further): the factor is ptw[o].
+// The table is laid out like one segment of the data, so its reads are as
+// coalesced as the data's and it stays in cache across segments.
+template <typename V> __device__ __forceinline__ V pre_twiddle(V v, int64_t o, int64_t istep, const void *ptw)
 {
     const tw_t<V> *t = (const tw_t<V> *)ptw;
-    const unsigned i = (unsigned)e * (unsigned)lp;
     if constexpr (std::is_same<V, c2x>::value) {
-        v.a = cmul(v.a, t[i]);
-        v.b = cmul(v.b, t[i + (unsigned)e]);
+        v.a = cmul(v.a, t[o]);
+        v.b = cmul(v.b, t[o + istep]);
         return v;
     } else {
-        return cmul(v, t[i]);
+        (void)istep;
+        return cmul(v, t[o]);
     }
 }
 
@@ -451,8 +451,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                     if (NBF % T == 0 || b < NBF) {
 #pragma unroll
                         for (int q = 0; q < R0; q++) {
-                            const int e = b + q * NBF;
-                            if (e > 0) v[u * R0 + q] = pre_twiddle(v[u * R0 + q], e, (int)lp, a.ptw);
+                            const int64_t o = (base - seg0) + (int64_t)(b + q * NBF) * S;
+                            v[u * R0 + q] = pre_twiddle(v[u * R0 + q], o, a.istep, a.ptw);
                         }
                     }
                 }
