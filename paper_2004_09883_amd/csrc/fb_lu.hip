@@ -32,19 +32,86 @@ __global__ void lu_init(int32_t *info)
     if (threadIdx.x == 0 && blockIdx.x == 0) info[0] = 0;
 }
 
+// ---- pivot search within a wavefront
+//
+// A candidate is (magnitude, row); the larger magnitude wins and equal
+// magnitudes go to the smaller row, so every reduction order finds the first
+// row of largest magnitude.  The all-reduce over 64 lanes exchanges with the
+// lanes l ^ 1, l ^ 2 (DPP quad permutations), 7 - l within 8 and 15 - l
+// within 16 (DPP half-row and row mirrors), then with the same lane of the
+// row r ^ 1 and r ^ 2 (permlane16 / permlane32 swaps): each step pairs
+// disjoint halves of a group, so after six steps every lane holds the
+// wave's best candidate.
+__device__ __forceinline__ bool beats(double ob, int oi, double b, int i)
+{
+    return (ob > b) | ((ob == b) & (oi < i));   // no short circuit: selects, not branches
+}
+__device__ __forceinline__ void better(double &b, int &i, double ob, int oi)
+{
+    const bool t = beats(ob, oi, b, i);
+    b = t ? ob : b;
+    i = t ? oi : i;
+}
+
+template <int CTRL> __device__ __forceinline__ int dpp_i(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ __forceinline__ double dpp_d(double x)
+{
+    const long long u = __double_as_longlong(x);
+    const int lo = dpp_i<CTRL>((int)u), hi = dpp_i<CTRL>((int)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// the same lane of row r ^ 1 (ROWS = 1) or r ^ 2 (ROWS = 2)
+template <int ROWS> __device__ __forceinline__ int row_partner_i(int x, int lane)
+{
+    if constexpr (ROWS == 1) {
+        const auto r = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)x, false, false);
+        return (int)((lane & 16) ? r[0] : r[1]);
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)x, false, false);
+        return (int)((lane & 32) ? r[0] : r[1]);
+    }
+}
+template <int ROWS> __device__ __forceinline__ double row_partner_d(double x, int lane)
+{
+    const long long u = __double_as_longlong(x);
+    const int lo = row_partner_i<ROWS>((int)u, lane), hi = row_partner_i<ROWS>((int)(u >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ void wave_best(double &b, int &i, int lane)
+{
+    better(b, i, dpp_d<0xB1>(b), dpp_i<0xB1>(i));     // quad_perm [1,0,3,2]: l ^ 1
+    better(b, i, dpp_d<0x4E>(b), dpp_i<0x4E>(i));     // quad_perm [2,3,0,1]: l ^ 2
+    better(b, i, dpp_d<0x141>(b), dpp_i<0x141>(i));   // row_half_mirror
+    better(b, i, dpp_d<0x140>(b), dpp_i<0x140>(i));   // row_mirror
+    better(b, i, row_partner_d<1>(b, lane), row_partner_i<1>(i, lane));
+    better(b, i, row_partner_d<2>(b, lane), row_partner_i<2>(i, lane));
+}
+
+struct PanelCand {
+    double best;
+    int row;
+    int pad;
+};
+
 __global__ void __launch_bounds__(LU_PANEL_THREADS)
     lu_panel(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb, int32_t *__restrict__ ipiv,
              int32_t *__restrict__ info)
 {
     constexpr int W = LU_PANEL_THREADS / 64;   // waves
-    // double-buffered by column parity: column j + 1 writes the other half, so
-    // the only barriers of a column are after the wave maxima and after the
-    // row exchange (a thread reaching column j + 1's first barrier has
-    // finished every read of column j - 1's buffers)
-    __shared__ double rowj[2][LU_NB], rowp[2][LU_NB];
-    __shared__ double wbest[2][W];
-    __shared__ int widx[2][W];
-    const int tid = threadIdx.x;
+    // One barrier per column.  Before it, each wave publishes its best
+    // candidate and that candidate's whole row, and the owner of row j
+    // publishes row j; after it, every thread picks the pivot among the W
+    // candidates and reads the rows it needs.  The buffers alternate with the
+    // column's parity: a thread that reaches column j + 1's barrier has
+    // finished every read of column j - 1's buffers.
+    __shared__ PanelCand cand[2][W];
+    __shared__ double crow[2][W][LU_NB];
+    __shared__ double rowj[2][LU_NB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = (int)(n - k);   // rows of the panel (<= LU_ROWS * LU_PANEL_THREADS, checked on the host)
     // thread 0 keeps the first zero pivot in a register (a global read per
     // column would stall every column's barrier on memory latency)
@@ -64,7 +131,8 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
         constexpr int j = decltype(jc)::value;
         if (j < nb) {   // uniform
             constexpr int h = j & 1;
-            // ---- pivot: the first row i >= j of largest |a[i][j]|
+            // ---- pivot candidates: the first row i >= j of largest |a[i][j]|,
+            // per thread, then per wave
             double best = -1.0;
             int bi = 0x7fffffff;
 #pragma unroll
@@ -78,58 +146,14 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
                     }
                 }
             }
-            {
-                // the wave's largest magnitude, then the smallest row holding it
-                double wm = best;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) wm = fmax(wm, __shfl_xor(wm, off));
-                int cand = best == wm ? bi : 0x7fffffff;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) cand = min(cand, __shfl_xor(cand, off));
-                best = wm;
-                bi = cand;
-            }
-            if ((tid & 63) == 0) {
-                wbest[h][tid >> 6] = best;
-                widx[h][tid >> 6] = bi;
-            }
-            __syncthreads();
-            // every wave reduces the W wave maxima: lane l < W takes entry l,
-            // then shuffle trees over W lanes; lane 0's result is made
-            // wave-uniform
-            double b = -1.0;
-            int p = 0x7fffffff;
-            {
-                const int lane = tid & 63;
-                if (lane < W) {
-                    b = wbest[h][lane];
-                    p = widx[h][lane];
-                }
-                double wm = b;
-#pragma unroll
-                for (int off = W / 2; off > 0; off >>= 1) wm = fmax(wm, __shfl_xor(wm, off));
-                int cand = b == wm ? p : 0x7fffffff;
-#pragma unroll
-                for (int off = W / 2; off > 0; off >>= 1) cand = min(cand, __shfl_xor(cand, off));
-                b = wm;
-                p = cand;
-                p = __builtin_amdgcn_readfirstlane(p);
-                const unsigned long long bb = (unsigned long long)__double_as_longlong(b);
-                const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)bb);
-                const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(bb >> 32));
-                b = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-            }
-            if (tid == 0) {
-                ipiv[k + j] = (int32_t)(k + p);
-                if (b == 0.0 && zero_at == 0) zero_at = (int32_t)(k + j + 1);
-            }
-            // ---- exchange rows j and p of the panel through LDS; rowp is the pivot row
+            wave_best(best, bi, lane);
+            if (lane == 0) cand[h][wave] = PanelCand{best, bi, 0};
 #pragma unroll
             for (int r = 0; r < LU_ROWS; r++) {
                 const int i = tid + LU_PANEL_THREADS * r;
-                if (i == p) {
+                if (i == bi) {
 #pragma unroll
-                    for (int c = 0; c < LU_NB; c++) rowp[h][c] = v[r][c];
+                    for (int c = 0; c < LU_NB; c++) crow[h][wave][c] = v[r][c];
                 }
                 if (i == j) {
 #pragma unroll
@@ -137,19 +161,37 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
                 }
             }
             __syncthreads();
+            // ---- the pivot: the best of the W wave candidates (the same
+            // sequence of comparisons in every thread)
+            double b = cand[h][0].best;
+            int p = cand[h][0].row, pw = 0;
+#pragma unroll
+            for (int w = 1; w < W; w++) {
+                const PanelCand cw = cand[h][w];
+                const bool t = beats(cw.best, cw.row, b, p);
+                b = t ? cw.best : b;
+                p = t ? cw.row : p;
+                pw = t ? w : pw;
+            }
+            if (tid == 0) {
+                ipiv[k + j] = (int32_t)(k + p);
+                if (b == 0.0 && zero_at == 0) zero_at = (int32_t)(k + j + 1);
+            }
+            const double *rowp = crow[h][pw];
+            // ---- exchange rows j and p
 #pragma unroll
             for (int r = 0; r < LU_ROWS; r++) {
                 const int i = tid + LU_PANEL_THREADS * r;
                 if (i == j) {
 #pragma unroll
-                    for (int c = 0; c < LU_NB; c++) v[r][c] = rowp[h][c];
+                    for (int c = 0; c < LU_NB; c++) v[r][c] = rowp[c];
                 } else if (i == p) {
 #pragma unroll
                     for (int c = 0; c < LU_NB; c++) v[r][c] = rowj[h][c];
                 }
             }
             // ---- scale the column below the pivot, update the panel's right part
-            const double piv = rowp[h][j];
+            const double piv = rowp[j];
             if (piv != 0.0) {
 #pragma unroll
                 for (int r = 0; r < LU_ROWS; r++) {
@@ -158,7 +200,7 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
                         const double l = v[r][j] / piv;
                         v[r][j] = l;
 #pragma unroll
-                        for (int c = j + 1; c < LU_NB; c++) v[r][c] -= l * rowp[h][c];
+                        for (int c = j + 1; c < LU_NB; c++) v[r][c] -= l * rowp[c];
                     }
                 }
             }
@@ -184,6 +226,13 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
 // column loads every touched row at once and stores each once, instead of
 // nb dependent swaps.  One thread per column: row accesses are coalesced.
 constexpr int LU_SWAP_THREADS = 64;
+// the value of x in lane l (l uniform over the wave)
+__device__ __forceinline__ int64_t lane_i64(int64_t x, int l)
+{
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)(uint64_t)x, l);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)((uint64_t)x >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 __global__ void __launch_bounds__(LU_SWAP_THREADS)
     lu_swap_trsm(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb, const int32_t *__restrict__ ipiv)
 {
@@ -205,8 +254,9 @@ __global__ void __launch_bounds__(LU_SWAP_THREADS)
         int64_t d = lane < nb ? k + lane : -1;
         int64_t sr = d;
         int cnt = nb;
+        // j and q are uniform, so every exchange is a scalar read of one lane
         for (int j = 0; j < nb; j++) {
-            const int64_t pr = __shfl(pv, j);
+            const int64_t pr = lane_i64(pv, j);
             int q;
             if (pr - k < nb) {
                 q = (int)(pr - k);   // inside the block (pivot rows are >= k + j)
@@ -219,7 +269,7 @@ __global__ void __launch_bounds__(LU_SWAP_THREADS)
                     if (lane == q) d = sr = pr;
                 }
             }
-            const int64_t sj = __shfl(sr, j), sq = __shfl(sr, q);
+            const int64_t sj = lane_i64(sr, j), sq = lane_i64(sr, q);
             if (lane == j) sr = sq;
             if (lane == q) sr = sj;
         }

@@ -152,6 +152,157 @@ __device__ __forceinline__ void mx_stage16(const float2 *__restrict__ tw, const 
     if constexpr (DST_LDS) __syncthreads();
 }
 
+// ---- register exchange between the vector-unit and the matrix-core layout
+//
+// In the vector-unit layout each lane holds one butterfly: its 16 inputs (or
+// outputs) in natural order, as four blocks of four complex values.  The
+// matrix-core operand layout above wants, for the 16 butterflies of row
+// gamma (lanes 16 gamma .. 16 gamma + 15), block g of butterfly (gamma, c) in
+// lane (c, g).  Both are related by a 4 x 4 transpose of (row, block) among
+// the four lanes of a column: block j of lane (c, r) trades places with block
+// r of lane (c, j).  It takes two rounds of row swaps: rows 0,1 <-> 2,3
+// (v_permlane32_swap) and rows 0 <-> 1, 2 <-> 3 (v_permlane16_swap), with no
+// LDS traffic, and it is its own inverse.
+
+// a: rows 2,3 <- rows 0,1 of b; b: rows 0,1 <- rows 2,3 of a
+__device__ __forceinline__ void swap_row_halves(float &a, float &b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+// a: rows 1,3 <- rows 0,2 of b; b: rows 0,2 <- rows 1,3 of a
+__device__ __forceinline__ void swap_odd_even_rows(float &a, float &b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ void row_block_transpose(float2 (&x)[4][4])
+{
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            swap_row_halves(x[j][i].x, x[j + 2][i].x);
+            swap_row_halves(x[j][i].y, x[j + 2][i].y);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j += 2) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            swap_odd_even_rows(x[j][i].x, x[j + 1][i].x);
+            swap_odd_even_rows(x[j][i].y, x[j + 1][i].y);
+        }
+    }
+}
+
+// One radix-16 stage on the matrix cores with register input (IN_REG: the
+// first stage of a pass, r[h][q] = input q of the lane's butterfly) and/or
+// register output (OUT_REG: the last stage, r[h][k] = output k).  The other
+// side is `src` or `dst` (LDS rows) at the positions of mx_stage16.  A lane
+// holding a pencil pair carries SETS = 2 butterflies (h = 0, 1: the pair's
+// two pencils, whose elements sit side by side in LDS and move as one 16-byte
+// access); who(l, pp, b) gives the pencil (pair) and butterfly index b held
+// by lane l of this wave.  Whole active wavefronts only; no barriers here.
+template <int N, int Ns, int TWOFF, bool IN_REG, bool OUT_REG, int SETS, class Who, class Src, class Dst>
+__device__ __forceinline__ void mx_stage16_reg(const float2 *__restrict__ tw, const MxConsts &A, int lane,
+                                               float2 (&r)[SETS][16], const Who &who, const Src &src,
+                                               const Dst &dst)
+{
+    static_assert(SETS == 1 || SETS == 2, "one pencil or a pencil pair per lane");
+    constexpr int NBF = N / 16;
+    const int c = lane & 15, g = lane >> 4;
+    float2 x[SETS][4][4];
+    if constexpr (IN_REG) {
+#pragma unroll
+        for (int h = 0; h < SETS; h++) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+#pragma unroll
+                for (int i = 0; i < 4; i++) x[h][j][i] = r[h][4 * j + i];
+            }
+            row_block_transpose(x[h]);
+        }
+    }
+#pragma unroll
+    for (int gm = 0; gm < 4; gm++) {
+        int pp, b;
+        who(16 * gm + c, pp, b);
+        if constexpr (!IN_REG) {
+            const auto hd = src.open(pp);
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                if constexpr (SETS == 2) src.load2(hd, b + (4 * g + i) * NBF, x[0][gm][i], x[1][gm][i]);
+                else x[0][gm][i] = src.load(hd, b + (4 * g + i) * NBF);
+            }
+        }
+        if constexpr (Ns > 1) {
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int q = 4 * g + i;
+                if (q > 0) {
+                    const float2 w = tw[TWOFF + (q - 1) * Ns + (b % Ns)];
+#pragma unroll
+                    for (int h = 0; h < SETS; h++) x[h][gm][i] = cmul(x[h][gm][i], w);
+                }
+            }
+        }
+        f32x4 yr[SETS], yi[SETS];
+#pragma unroll
+        for (int h = 0; h < SETS; h++) {
+            bf16x8 xh, xl;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const __bf16 hr = (__bf16)x[h][gm][i].x, hi = (__bf16)x[h][gm][i].y;
+                xh[2 * i] = hr;
+                xh[2 * i + 1] = hi;
+                xl[2 * i] = (__bf16)(x[h][gm][i].x - (float)hr);
+                xl[2 * i + 1] = (__bf16)(x[h][gm][i].y - (float)hi);
+            }
+            yr[h] = mx_dot(A.ar, xh, xl);
+            yi[h] = mx_dot(A.ai, xh, xl);
+        }
+        if constexpr (OUT_REG) {
+#pragma unroll
+            for (int h = 0; h < SETS; h++) {
+#pragma unroll
+                for (int e = 0; e < 4; e++) x[h][gm][e] = make_float2(yr[h][e], yi[h][e]);
+            }
+        } else {
+            const int idx = (b / Ns) * Ns * 16 + (b % Ns);
+            const auto hd = dst.open(pp);
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                if constexpr (SETS == 2)
+                    dst.store2(hd, idx + (4 * g + e) * Ns, make_float2(yr[0][e], yi[0][e]),
+                               make_float2(yr[1][e], yi[1][e]));
+                else dst.store(hd, idx + (4 * g + e) * Ns, make_float2(yr[0][e], yi[0][e]));
+            }
+        }
+    }
+    if constexpr (OUT_REG) {
+#pragma unroll
+        for (int h = 0; h < SETS; h++) {
+            row_block_transpose(x[h]);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+#pragma unroll
+                for (int i = 0; i < 4; i++) r[h][4 * j + i] = x[h][j][i];
+            }
+        }
+    }
+}
+
+// Neither a source nor a destination (the register side of mx_stage16_reg).
+struct MxNone {
+    __device__ __forceinline__ float2 *open(int) const { return nullptr; }
+    __device__ __forceinline__ float2 load(float2 *, int) const { return make_float2(0.f, 0.f); }
+    __device__ __forceinline__ void store(float2 *, int, float2) const {}
+};
+
 // LDS rows of a tile as a source or destination of a matrix-core stage.
 struct MxLds {
     float2 *lds;
@@ -170,6 +321,17 @@ struct MxLdsPair {
     __device__ __forceinline__ float2 *open(int pp) const { return lds + (pp >> 1) * 2 * LS + (pp & 1); }
     __device__ __forceinline__ float2 load(float2 *row, int pos) const { return row[2 * lds_pos(pos)]; }
     __device__ __forceinline__ void store(float2 *row, int pos, float2 v) const { row[2 * lds_pos(pos)] = v; }
+    // both pencils of the pair (row opened with an even pp), one 16-byte access
+    __device__ __forceinline__ void load2(float2 *row, int pos, float2 &a, float2 &b) const
+    {
+        const float4 v = *(const float4 *)(row + 2 * lds_pos(pos));
+        a = make_float2(v.x, v.y);
+        b = make_float2(v.z, v.w);
+    }
+    __device__ __forceinline__ void store2(float2 *row, int pos, float2 a, float2 b) const
+    {
+        *(float4 *)(row + 2 * lds_pos(pos)) = make_float4(a.x, a.y, b.x, b.y);
+    }
 };
 
 }  // namespace fb

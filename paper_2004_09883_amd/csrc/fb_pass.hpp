@@ -24,9 +24,12 @@
 // consecutive elements.
 //
 // MX (complex64 only): the radix-16 stages run on the matrix cores
-// (fb_mfma.hpp); the first and last of them read and write global memory
-// themselves where the tile allows it (see MxStage::direct), the others work
-// LDS to LDS.  The remaining stages and the twiddles stay on the vector units.
+// (fb_mfma.hpp).  A first matrix-core stage takes its inputs straight from
+// the registers the global loads filled, and a last one leaves its outputs in
+// the registers the global stores read, by a lane exchange within the
+// wavefront (MxStage::regs); the others work LDS to LDS, as the vector stages
+// exchange through LDS.  The remaining stages and the twiddles stay on the
+// vector units.
 #pragma once
 #include "fb_device.hpp"
 #include "fb_internal.hpp"
@@ -140,6 +143,16 @@ template <typename V> __device__ __forceinline__ V pre_twiddle(V v, int64_t o, i
 #ifndef FB_MX_DIRECT
 #define FB_MX_DIRECT 0
 #endif
+// Whether the first / last matrix-core stage of a pass takes its inputs from /
+// leaves its outputs in the vector-unit registers (a lane exchange, see
+// mx_stage16_reg) instead of an LDS round trip.
+#ifndef FB_MX_REGS
+#define FB_MX_REGS 1
+#endif
+// The same for the last stage of pencil-pair tiles (FB_MX_REGS_OUT_PAIRS).
+#ifndef FB_MX_REGS_OUT_PAIRS
+#define FB_MX_REGS_OUT_PAIRS 1
+#endif
 
 template <typename V, int N, bool CONTIG, bool MX> struct MxStage {
     // whether stage s runs on the matrix cores
@@ -152,6 +165,8 @@ template <typename V, int N, bool CONTIG, bool MX> struct MxStage {
     {
         return FB_MX_DIRECT && MX && std::is_same<V, float2>::value && (CONTIG || PassCfg<V, N, CONTIG>::P % 16 == 0);
     }
+    static constexpr bool regs() { return FB_MX_REGS && MX && !direct(); }
+    static constexpr bool regs_out() { return regs() && (FB_MX_REGS_OUT_PAIRS || !std::is_same<V, c2x>::value); }
 };
 
 // Butterfly numbering of the matrix-core stages: beta -> (pencil, b).
@@ -359,6 +374,9 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
     // first / last matrix-core stage reads / writes global memory itself
     constexpr bool MX_IN = MXS::at(0) && MXS::direct() && !MULTI;
     constexpr bool MX_OUT = MXS::at(NST - 1) && MXS::direct() && !MULTI;
+    // first / last matrix-core stage works on the registers
+    constexpr bool MX_RIN = MXS::at(0) && MXS::regs();
+    constexpr bool MX_ROUT = MXS::at(NST - 1) && MXS::regs_out();
     constexpr int R0 = RP.r[0];
     constexpr int NBF0 = N / R0;
     constexpr int U0 = (NBF0 + T - 1) / T;
@@ -458,7 +476,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                 }
             }
         }
-        if constexpr (MXS::at(0) && !MX_IN) {
+        if constexpr (MXS::at(0) && !MX_IN && !MX_RIN) {
             // the matrix-core stage reads its inputs from LDS in natural order
 #pragma unroll
             for (int u = 0; active && u < U; u++) {
@@ -497,7 +515,54 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                 }
                 __syncthreads();
             }
-            if constexpr (std::is_same<V, float2>::value) {
+            constexpr bool RIN = (s == 0) && MX_RIN;
+            constexpr bool ROUT = (s == NST - 1) && MX_ROUT;
+            if constexpr (RIN || ROUT) {
+                // lane l of the wave holds the butterfly of thread (tid & ~63) + l
+                constexpr int SETS = PAIR ? 2 : 1;
+                float2 r[SETS][16];
+                if constexpr (RIN) {
+#pragma unroll
+                    for (int q = 0; q < 16; q++) {
+                        if constexpr (PAIR) {
+                            r[0][q] = v[q].a;
+                            r[1][q] = v[q].b;
+                        } else if constexpr (std::is_same<V, float2>::value) {
+                            r[0][q] = v[q];
+                        }
+                    }
+                }
+                auto who = [&](int l, int &pq, int &b) {
+                    const int tt = (tid & ~63) + l;
+                    b = CONTIG ? tt % T : tt / P;
+                    const int pl = CONTIG ? tt / T : tt % P;
+                    pq = PAIR ? 2 * pl : pl;   // a pair's first pencil
+                };
+                if (active) {
+                    if constexpr (PAIR) {
+                        const MxLdsPair L{(float2 *)lds, LS};
+                        mx_stage16_reg<N, Ns, RP.twoff[s], RIN, ROUT, SETS>((const float2 *)tw, mxc, tid & 63, r,
+                                                                            who, L, L);
+                    } else {
+                        const MxLds L{(float2 *)lds, LS};
+                        mx_stage16_reg<N, Ns, RP.twoff[s], RIN, ROUT, SETS>((const float2 *)tw, mxc, tid & 63, r,
+                                                                            who, L, L);
+                    }
+                }
+                if constexpr (ROUT) {
+#pragma unroll
+                    for (int q = 0; q < 16; q++) {
+                        if constexpr (PAIR) {
+                            v[q].a = r[0][q];
+                            v[q].b = r[1][q];
+                        } else if constexpr (std::is_same<V, float2>::value) {
+                            v[q] = r[0][q];
+                        }
+                    }
+                } else {
+                    __syncthreads();   // the outputs are in LDS for the next stage
+                }
+            } else if constexpr (std::is_same<V, float2>::value) {
                 constexpr bool IN_G = (s == 0) && MX_IN;
                 constexpr bool OUT_G = (s == NST - 1) && MX_OUT;
                 const MxLds ldsio{(float2 *)lds, LS};
@@ -580,7 +645,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
         constexpr int RL = RP.r[NST - 1];
         constexpr int NBF = N / RL;
         constexpr int U = (NBF + T - 1) / T;
-        if constexpr (MXS::at(NST - 1) && !MX_OUT) {
+        if constexpr (MXS::at(NST - 1) && !MX_OUT && !MX_ROUT) {
             // the matrix-core stage left the result in LDS in natural order
 #pragma unroll
             for (int u = 0; active && u < U; u++) {
