@@ -272,6 +272,19 @@ int fb_server_poll(fb_server *s, fb_result *out, double *sums, int sums_cap, voi
 /* Requests submitted and not yet taken by fb_server_poll's producer side. */
 int64_t fb_server_in_flight(fb_server *s);
 int fb_server_stats(fb_server *s, fb_server_info *info);
+/* Admission order (either way a request starts only when a stream slot is
+ * free and its bytes fit the budget, and the chosen request waits for that):
+ *   FB_SERVE_FIFO (the default): the oldest queued request first;
+ *   FB_SERVE_DEADLINE: the request with the earliest arrival time plus
+ *     estimated service time first, the estimate being its bytes under the
+ *     pass model (5 + ceil(steps/8) + 5 steps grids of E N bytes) at a
+ *     nominal 5 TB/s.  A short request overtakes long ones that arrived at
+ *     most its estimated saving earlier, and no request is overtaken by one
+ *     that arrived after its own estimated completion, so none starves.
+ * May be changed while requests run (it applies to later admissions).
+ * Returns FB_OK, or FB_ERR_INVALID_ARG for a NULL server or another value. */
+enum { FB_SERVE_FIFO = 0, FB_SERVE_DEADLINE = 1 };
+int fb_server_set_policy(fb_server *s, int policy);
 /* Finishes queued and running requests, then releases everything. */
 void fb_server_destroy(fb_server *s);
 

@@ -1,9 +1,10 @@
 // fb_serve.cpp -- the serving form: a request loop that runs spectral-block
 // requests of mixed shapes and dtypes on one GPU with continuous batching.
 //
-// A worker thread owns the device side.  Submitted requests wait in a FIFO;
-// the worker admits the head whenever a stream slot is free and the bytes of
-// the request fit in the HBM budget, so requests that arrive while others
+// A worker thread owns the device side.  Submitted requests wait in a queue;
+// the worker admits the next one (the oldest, or under FB_SERVE_DEADLINE the
+// one with the earliest arrival plus estimated service time) whenever a
+// stream slot is free and its bytes fit in the HBM budget, so requests that arrive while others
 // are on the GPU start as soon as a slot and memory free up and their work
 // overlaps on the device (one HIP stream per slot).  Plans are cached per
 // (shape, dtype) and device buffers are pooled by size, so both stay
@@ -95,6 +96,7 @@ struct fb_server {
     std::atomic<bool> stop{false};
     int64_t next_id = 0;
     int64_t in_flight = 0;
+    std::atomic<int> policy{FB_SERVE_FIFO};
     int last_error = FB_OK;
     std::string last_msg;
     int max_concurrent = 0;
@@ -117,6 +119,33 @@ size_t request_bytes(const fb_request &r)
 {
     const size_t n = (size_t)(r.nx * r.ny * r.nz);
     return (1 + (size_t)chunk_of(r.steps)) * n * esize_of(r.dtype) + sums_bytes_of(r.steps);
+}
+
+// Estimated service time of a request alone on the device: the grids its
+// passes move (input generated in the first forward pass: 5 grids for the
+// forward transform; one read of the spectrum per chunk of steps; 5 grids per
+// step) at a nominal 5 TB/s.
+double service_estimate_s(const fb_request &r)
+{
+    const double grid = (double)(r.nx * r.ny * r.nz) * (double)esize_of(r.dtype);
+    const double chunks = (double)((r.steps + kChunk - 1) / kChunk);
+    return grid * (5.0 + chunks + 5.0 * r.steps) / 5e12;
+}
+
+// Index of the queued request to admit next (the queue is not empty).
+size_t next_index(fb_server *s)
+{
+    if (s->policy.load() != FB_SERVE_DEADLINE) return 0;
+    size_t best = 0;
+    double key = 0;
+    for (size_t i = 0; i < s->queue.size(); i++) {
+        const double k = s->queue[i].t_arrival + service_estimate_s(s->queue[i].req);
+        if (i == 0 || k < key) {
+            best = i;
+            key = k;
+        }
+    }
+    return best;
 }
 
 void *pool_get(fb_server *s, size_t bytes, hipError_t &e)
@@ -252,13 +281,15 @@ void worker_loop(fb_server *s)
                 idle = false;
             }
         }
-        // admissions (FIFO)
+        // admissions, in the order of the policy
         for (;;) {
             Pending head;
+            size_t hi;
             {
                 std::lock_guard<std::mutex> lk(s->mu);
                 if (s->queue.empty()) break;
-                head = s->queue.front();
+                hi = next_index(s);
+                head = s->queue[hi];
             }
             Slot *free_slot = nullptr;
             for (Slot &sl : s->slots)
@@ -269,7 +300,7 @@ void worker_loop(fb_server *s)
             if (!free_slot || !fits(s, head.req)) break;
             {
                 std::lock_guard<std::mutex> lk(s->mu);
-                s->queue.pop_front();
+                s->queue.erase(s->queue.begin() + (std::ptrdiff_t)hi);   // only this thread removes entries
             }
             Slot &sl = *free_slot;
             sl.busy = true;
@@ -375,6 +406,13 @@ int64_t fb_server_in_flight(fb_server *s)
     if (!s) return FB_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(s->mu);
     return s->in_flight;
+}
+
+int fb_server_set_policy(fb_server *s, int policy)
+{
+    if (!s || (policy != FB_SERVE_FIFO && policy != FB_SERVE_DEADLINE)) return FB_ERR_INVALID_ARG;
+    s->policy.store(policy);
+    return FB_OK;
 }
 
 int fb_server_stats(fb_server *s, fb_server_info *info)

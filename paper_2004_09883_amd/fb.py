@@ -35,10 +35,12 @@ EXPORTS = ("fb_version", "fb_last_error", "fb_describe_shape", "fb_fft3d_plan", 
            "fb_profile_enable", "fb_profile_report", "fb_batch_plan", "fb_batch_destroy", "fb_batch_elements",
            "fb_batch_offsets", "fb_batch_workspace_bytes", "fb_batch_launches", "fb_batch_describe",
            "fb_batch_exec", "fb_server_create", "fb_server_submit", "fb_server_poll",
-           "fb_server_in_flight", "fb_server_stats", "fb_server_destroy")
+           "fb_server_in_flight", "fb_server_stats", "fb_server_set_policy", "fb_server_destroy")
 
 
 FB_SERVE_MAX_STEPS = 64
+FB_SERVE_FIFO = 0
+FB_SERVE_DEADLINE = 1
 
 
 class FbRequest(ctypes.Structure):
@@ -113,6 +115,7 @@ def load():
         "fb_server_poll": (i32, [vp, ctypes.POINTER(FbResult), ctypes.POINTER(dbl), i32, vp, ctypes.c_size_t]),
         "fb_server_in_flight": (i64, [vp]),
         "fb_server_stats": (i32, [vp, ctypes.POINTER(FbServerInfo)]),
+        "fb_server_set_policy": (i32, [vp, i32]),
         "fb_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -382,12 +385,18 @@ def fb_batch_exec(batch: Batch, x_in, x_out, workspace, direction: int = FB_FORW
 class Server:
     """Owns an fb_server*: the continuous-batching request loop."""
 
-    def __init__(self, budget_bytes: int, n_streams: int = 8):
+    def __init__(self, budget_bytes: int, n_streams: int = 8, policy: int = FB_SERVE_FIFO):
         self._lib = load()
         h = self._lib.fb_server_create(int(budget_bytes), int(n_streams))
         if not h:
             raise FbError(FB_ERR_INVALID_ARG, "fb_server_create failed (budget >= 1 MiB, 1..64 streams, a device)")
         self.handle = h
+        if policy != FB_SERVE_FIFO:
+            self.set_policy(policy)
+
+    def set_policy(self, policy: int):
+        """FB_SERVE_FIFO or FB_SERVE_DEADLINE (see include/fb.h)."""
+        _check(self._lib.fb_server_set_policy(self.handle, int(policy)))
 
     def submit(self, nx, ny, nz, dtype, steps, alpha, seed, request_key, want_grid=False) -> int:
         r = FbRequest(nx, ny, nz, dtype, steps, alpha, seed & 0xFFFFFFFFFFFFFFFF, request_key, 1 if want_grid else 0)

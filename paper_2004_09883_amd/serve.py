@@ -38,13 +38,13 @@ def request_flops(shape, steps: int) -> float:
 
 def run_serving(rate: float = 2000.0, duration: float = 10.0, warmup: float = 1.0, budget_bytes: float = 200e9,
                 n_streams: int = 8, seed_arrivals: int = 5, seed_payload: int = 4, alpha: float = 1e-6,
-                poll_every: int = 4) -> dict:
+                poll_every: int = 4, policy: int = fb.FB_SERVE_FIFO) -> dict:
     count = int(math.ceil((warmup + duration) * rate * 1.2)) + 16
     w = inputs.serving_workload(count, rate, seed_arrivals)
     keep = w["arrival"] < warmup + duration
     arrival = w["arrival"][keep]
     n_req = len(arrival)
-    server = fb.Server(int(budget_bytes), n_streams)
+    server = fb.Server(int(budget_bytes), n_streams, policy)
     results = {}
     meta = {}
 
@@ -111,6 +111,7 @@ def run_serving(rate: float = 2000.0, duration: float = 10.0, warmup: float = 1.
         "service_p50_ms": round(float(np.percentile(svc, 50)) * 1e3, 3),
         "service_p99_ms": round(float(np.percentile(svc, 99)) * 1e3, 3),
         "streams": n_streams,
+        "policy": "deadline" if policy == fb.FB_SERVE_DEADLINE else "fifo",
         "budget_bytes": int(budget_bytes),
         "peak_device_bytes": int(stats["peak_allocated"]),
         "max_concurrent": int(stats["max_concurrent"]),

@@ -79,6 +79,7 @@ def test_null_plan_calls_are_rejected():
     assert lib.fb_spectral_step(None, 16, 4096, 1e-6, 1.0, None, None) == fb.FB_ERR_INVALID_ARG
     assert lib.fb_fill_uniform(None, 16, 1, None) == fb.FB_ERR_INVALID_ARG
     assert lib.fb_plan_device_bytes(None) == 0
+    assert lib.fb_server_set_policy(None, fb.FB_SERVE_DEADLINE) == fb.FB_ERR_INVALID_ARG
     lib.fb_fft3d_destroy(None)   # NULL-safe
 
 

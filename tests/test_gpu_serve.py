@@ -102,6 +102,39 @@ def test_budget_admission():
     server.close()
 
 
+@pytest.mark.parametrize("policy", [fb.FB_SERVE_FIFO, fb.FB_SERVE_DEADLINE])
+def test_admission_policy_order(policy):
+    """One stream slot, so admissions are strictly one after the other: a
+    long request runs while a second long one and then a short one queue.
+    FIFO admits them in arrival order; the deadline policy lets the short one
+    (arrival + estimated service earlier) overtake.  Results do not depend on
+    the order."""
+    server = fb.Server(16 << 30, 1, policy)
+    big = ((256, 256, 256), fb.FB_C64, 4)
+    a = server.submit(*big[0], big[1], big[2], ALPHA, SEED, 200)
+    while server.stats()["queued"] > 0:   # a is admitted (and runs for milliseconds)
+        pass
+    b = server.submit(*big[0], big[1], big[2], ALPHA, SEED, 201)
+    c = server.submit(32, 32, 32, fb.FB_C128, 1, ALPHA, SEED, 202)
+    res = wait_for(server, 3, 0)
+    server.close()
+    assert all(r["status"] == 0 for r in res.values())
+    assert res[a]["t_admit"] <= min(res[b]["t_admit"], res[c]["t_admit"])
+    if policy == fb.FB_SERVE_FIFO:
+        assert res[b]["t_admit"] < res[c]["t_admit"]
+    else:
+        assert res[c]["t_admit"] < res[b]["t_admit"]
+    # the same requests alone give the same checksums
+    solo = fb.Server(16 << 30, 1)
+    ids = {solo.submit(*big[0], big[1], big[2], ALPHA, SEED, 201): b, solo.submit(32, 32, 32, fb.FB_C128, 1, ALPHA, SEED, 202): c}
+    ref = wait_for(solo, 2, 0)
+    solo.close()
+    for rid, orig in ids.items():
+        assert ref[rid]["checksums"] == res[orig]["checksums"]
+    with pytest.raises(fb.FbError):
+        fb.Server(1 << 30, 1).set_policy(7)
+
+
 def test_submit_validation():
     server = fb.Server(1 << 30, 2)
     for bad in (dict(nx=5, ny=4, nz=4, dtype=fb.FB_C64, steps=1), dict(nx=4, ny=4, nz=4, dtype=7, steps=1),
