@@ -40,10 +40,10 @@ namespace fb {
 
 __device__ __forceinline__ int64_t signed_k(int64_t i, int64_t n) { return (2 * i >= n) ? i - n : i; }
 
-template <typename V, int N, bool CONTIG> struct PassCfg {
+template <typename V, int N, bool CONTIG, bool MX = false> struct PassCfg {
     static constexpr RadixPlan RP = radix_plan(N);
     static constexpr int T = threads_per_pencil(N);
-    static constexpr int P = pencils_per_wg(N, CONTIG, (int)sizeof(V));
+    static constexpr int P = pencils_per_wg(N, CONTIG, (int)sizeof(V), MX);
     static constexpr int THREADS = P * T;
     static constexpr int M = regs_per_thread(N);
     static constexpr int LS = lds_pencil_stride(N);
@@ -55,7 +55,7 @@ template <typename V, int N, bool CONTIG> struct PassCfg {
 // stage, 16 elements per thread and whole wavefronts.
 template <typename V, int N, bool CONTIG> constexpr bool mx_capable()
 {
-    using Cfg = PassCfg<V, N, CONTIG>;
+    using Cfg = PassCfg<V, N, CONTIG, true>;
     bool has16 = false;
     for (int s = 0; s < Cfg::RP.count; s++) has16 = has16 || Cfg::RP.r[s] == 16;
     const bool c64 = std::is_same<V, float2>::value || (std::is_same<V, c2x>::value && !CONTIG);
@@ -163,7 +163,7 @@ template <typename V, int N, bool CONTIG, bool MX> struct MxStage {
     // pencils fit in the tile (they are 16 consecutive elements)
     static constexpr bool direct()
     {
-        return FB_MX_DIRECT && MX && std::is_same<V, float2>::value && (CONTIG || PassCfg<V, N, CONTIG>::P % 16 == 0);
+        return FB_MX_DIRECT && MX && std::is_same<V, float2>::value && (CONTIG || PassCfg<V, N, CONTIG, MX>::P % 16 == 0);
     }
     static constexpr bool regs() { return FB_MX_REGS && MX && !direct(); }
     static constexpr bool regs_out() { return regs() && (FB_MX_REGS_OUT_PAIRS || !std::is_same<V, c2x>::value); }
@@ -335,7 +335,7 @@ __device__ __forceinline__ void store_tile_contiguous(const PassArgs &a, int64_t
 template <typename V, int N, bool CONTIG, bool MX, bool MULTI = false>
 __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int tid, V *lds, real_t<V> *gtab)
 {
-    using Cfg = PassCfg<V, N, CONTIG>;
+    using Cfg = PassCfg<V, N, CONTIG, MX>;
     using R = real_t<V>;
     constexpr RadixPlan RP = Cfg::RP;
     constexpr int T = Cfg::T, P = Cfg::P, M = Cfg::M, LS = Cfg::LS;
@@ -696,9 +696,9 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
 }
 
 template <typename V, int N, bool CONTIG, bool MX>
-__global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) FB_OCCUPANCY fft_pass(PassArgs a)
+__global__ void __launch_bounds__((PassCfg<V, N, CONTIG, MX>::THREADS)) FB_OCCUPANCY fft_pass(PassArgs a)
 {
-    using Cfg = PassCfg<V, N, CONTIG>;
+    using Cfg = PassCfg<V, N, CONTIG, MX>;
     __shared__ V lds[Cfg::P * Cfg::LS];
     __shared__ real_t<V> gtab[CONTIG ? N : 1];
     pass_tile<V, N, CONTIG, MX>(a, blockIdx.x, threadIdx.x, lds, gtab);
@@ -708,9 +708,9 @@ __global__ void __launch_bounds__((PassCfg<V, N, CONTIG>::THREADS)) FB_OCCUPANCY
 // once and output j (evolution constant ev_cs[j]) is written at
 // out + j out_step, for j < nout.
 template <typename V, int N, bool MX>
-__global__ void __launch_bounds__((PassCfg<V, N, true>::THREADS)) FB_OCCUPANCY fft_pass_multi(PassArgs a)
+__global__ void __launch_bounds__((PassCfg<V, N, true, MX>::THREADS)) FB_OCCUPANCY fft_pass_multi(PassArgs a)
 {
-    using Cfg = PassCfg<V, N, true>;
+    using Cfg = PassCfg<V, N, true, MX>;
     __shared__ V lds[Cfg::P * Cfg::LS];
     __shared__ real_t<V> gtab[N];
     pass_tile<V, N, true, MX, true>(a, blockIdx.x, threadIdx.x, lds, gtab);

@@ -9,7 +9,7 @@ namespace fb {
 
 template <typename V, int N, bool CONTIG, bool MX> hipError_t launch_pass(const PassArgs &a, hipStream_t st)
 {
-    using Cfg = PassCfg<V, N, CONTIG>;
+    using Cfg = PassCfg<V, N, CONTIG, MX>;
     constexpr int64_t UNIT = std::is_same<V, c2x>::value ? 2 : 1;   // pencils per tile slot
     const int64_t blocks = (a.npencils + UNIT * Cfg::P - 1) / (UNIT * Cfg::P);
     if (blocks <= 0) return hipSuccess;
@@ -22,8 +22,9 @@ template <typename V, int N, bool CONTIG, bool MX> hipError_t launch_pass(const 
 template <typename V, int N, bool CONTIG> PassInfo pass_info_k(bool mx)
 {
     using Cfg = PassCfg<V, N, CONTIG>;
+    using CfgM = PassCfg<V, N, CONTIG, true>;
     if constexpr (mx_capable<V, N, CONTIG>()) {
-        if (mx) return {&launch_pass<V, N, CONTIG, true>, Cfg::P, Cfg::THREADS, 1};
+        if (mx) return {&launch_pass<V, N, CONTIG, true>, CfgM::P, CfgM::THREADS, 1};
     }
     return {&launch_pass<V, N, CONTIG, false>, Cfg::P, Cfg::THREADS, 0};
 }
@@ -42,8 +43,9 @@ template <typename V, int N> PassInfo pass_info(bool contig, bool mx)
 template <int N> PassInfo pass_info_pair(bool mx)
 {
     using Cfg = PassCfg<c2x, N, false>;
+    using CfgM = PassCfg<c2x, N, false, true>;
     if constexpr (mx_capable<c2x, N, false>()) {
-        if (mx) return {&launch_pass<c2x, N, false, true>, 2 * Cfg::P, Cfg::THREADS, 1};
+        if (mx) return {&launch_pass<c2x, N, false, true>, 2 * CfgM::P, CfgM::THREADS, 1};
     }
     return {&launch_pass<c2x, N, false, false>, 2 * Cfg::P, Cfg::THREADS, 0};
 }
@@ -60,7 +62,7 @@ inline PassInfo find_pass_pair_t(int n, bool mx)
 
 template <typename V, int N, bool MX> hipError_t launch_pass_multi(const PassArgs &a, hipStream_t st)
 {
-    using Cfg = PassCfg<V, N, true>;
+    using Cfg = PassCfg<V, N, true, MX>;
     const int64_t blocks = (a.npencils + Cfg::P - 1) / Cfg::P;
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL((fft_pass_multi<V, N, MX>), dim3((unsigned)blocks), dim3(Cfg::THREADS), 0, st, a);
@@ -72,8 +74,9 @@ template <typename V, int N, bool MX> hipError_t launch_pass_multi(const PassArg
 template <typename V, int N> PassInfo pass_info_multi(bool mx)
 {
     using Cfg = PassCfg<V, N, true>;
+    using CfgM = PassCfg<V, N, true, true>;
     if constexpr (mx_capable<V, N, true>()) {
-        if (mx) return {&launch_pass_multi<V, N, true>, Cfg::P, Cfg::THREADS, 1};
+        if (mx) return {&launch_pass_multi<V, N, true>, CfgM::P, CfgM::THREADS, 1};
     }
     return {&launch_pass_multi<V, N, false>, Cfg::P, Cfg::THREADS, 0};
 }

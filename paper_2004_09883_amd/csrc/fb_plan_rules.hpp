@@ -77,7 +77,13 @@ constexpr int lds_pencil_stride(int n)
 
 // Build-time tuning knobs (defaults are the measured best on MI355X).
 #ifndef FB_LDS_CONTIG_KB
-#define FB_LDS_CONTIG_KB 40
+#define FB_LDS_CONTIG_KB 40   // contiguous complex64 passes
+#endif
+#ifndef FB_LDS_CONTIG16_KB
+#define FB_LDS_CONTIG16_KB 20   // contiguous complex128 passes: one wavefront per tile at n = 128, 256
+#endif
+#ifndef FB_LDS_CONTIG_MX_KB
+#define FB_LDS_CONTIG_MX_KB 20   // contiguous complex64 matrix-core passes
 #endif
 #ifndef FB_LDS_STRIDED_KB
 #define FB_LDS_STRIDED_KB 72
@@ -92,21 +98,30 @@ constexpr int lds_pencil_stride(int n)
 #define FB_CONTIG_THREADS 256
 #endif
 
-constexpr int lds_budget_bytes(bool contig) { return contig ? FB_LDS_CONTIG_KB * 1024 : FB_LDS_STRIDED_KB * 1024; }
+constexpr int lds_budget_bytes(bool contig, int esize, bool mx = false)
+{
+    return !contig     ? FB_LDS_STRIDED_KB * 1024
+           : esize == 16 ? FB_LDS_CONTIG16_KB * 1024
+           : mx          ? FB_LDS_CONTIG_MX_KB * 1024
+                         : FB_LDS_CONTIG_KB * 1024;
+}
 
 constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
 
-constexpr bool pencils_fit(int P, int n, bool contig, int esize)
+constexpr bool pencils_fit(int P, int n, bool contig, int esize, bool mx = false)
 {
-    return P * threads_per_pencil(n) <= 1024 && P * lds_pencil_stride(n) * esize <= lds_budget_bytes(contig);
+    return P * threads_per_pencil(n) <= 1024 && P * lds_pencil_stride(n) * esize <= lds_budget_bytes(contig, esize, mx);
 }
 
 // Pencils per workgroup.  Contiguous passes aim for 256 threads; strided
 // passes aim for 16 (c128) / 32 (c64) adjacent pencils so that every row
 // access is a 256-byte segment.  P is then moved to a multiple of
 // 64 / gcd(T, 64) so that the workgroup is whole wavefronts, when that fits;
-// finally it is capped by 1024 threads and by the LDS budget.
-constexpr int pencils_per_wg(int n, bool contig, int esize)
+// finally it is capped by 1024 threads and by the LDS budget.  A
+// matrix-core pass (mx) takes the budget of its own kind only where the tile
+// stays whole wavefronts (which the matrix-core stages need); otherwise that
+// of the vector-unit pass.
+constexpr int pencils_per_wg_b(int n, bool contig, int esize, bool mx)
 {
     const int T = threads_per_pencil(n);
     int P = contig ? (FB_CONTIG_THREADS / T > 0 ? FB_CONTIG_THREADS / T : 1)
@@ -116,10 +131,18 @@ constexpr int pencils_per_wg(int n, bool contig, int esize)
     if (P % m) {
         const int down = (P / m) * m, up = down + m;
         if (down > 0) P = down;
-        else if (pencils_fit(up, n, contig, esize)) P = up;
+        else if (pencils_fit(up, n, contig, esize, mx)) P = up;
     }
-    while (P > 1 && !pencils_fit(P, n, contig, esize)) P /= 2;
+    while (P > 1 && !pencils_fit(P, n, contig, esize, mx)) P /= 2;
     return P;
+}
+constexpr int pencils_per_wg(int n, bool contig, int esize, bool mx = false)
+{
+    if (mx) {
+        const int P = pencils_per_wg_b(n, contig, esize, true);
+        if ((P * threads_per_pencil(n)) % 64 == 0) return P;
+    }
+    return pencils_per_wg_b(n, contig, esize, false);
 }
 
 }  // namespace fb

@@ -98,3 +98,24 @@ def test_batch_workload_4096_plus_64x512x512():
             assert e < TOL, (persistent, i, n, e)
         print(f"batch workload persistent={persistent}: {len(sample)} transforms checked, worst rel L2 {worst:.2e}",
               flush=True)
+
+
+@pytest.mark.parametrize("lens,n2d,side", [([], 2, 64), ([196608], 0, 0), ([2], 0, 0), ([3] * 5, 0, 0),
+                                           ([24576, 24576], 1, 512), ([4096] * 3 + [8], 0, 0)])
+def test_batch_edge_shapes(lens, n2d, side):
+    """Only 2D transforms, a single transform of the largest length, a single
+    length-2 transform, several tiny transforms, one long length plus one 2D
+    transform: both modes against the oracle, and equal to each other."""
+    print(f"batch edge lens={lens[:4]} n2d={n2d} side={side}", flush=True)
+    batch = fb.Batch(lens, n2d=n2d, side2d=side)
+    x = packed_input(batch, 11)
+    outs = []
+    for persistent in (False, True):
+        got = run(batch, x, fb.FB_FORWARD, persistent, False)
+        for i in range(len(lens) + n2d):
+            o = batch.offsets[i]
+            n = lens[i] if i < len(lens) else side * side
+            e = rel_l2(got[o:o + n].astype(np.complex128), ref_transform(batch, x, i, fb.FB_FORWARD))
+            assert e < TOL, (persistent, i, n, e)
+        outs.append(got)
+    assert np.array_equal(outs[0], outs[1])
