@@ -23,8 +23,11 @@
 
 namespace fb {
 
-constexpr int LU_PANEL_THREADS = 512;
-constexpr int LU_ROWS = 4;   // rows of the panel per thread
+#ifndef FB_LU_PANEL_THREADS
+#define FB_LU_PANEL_THREADS 512
+#endif
+constexpr int LU_PANEL_THREADS = FB_LU_PANEL_THREADS;
+constexpr int LU_ROWS = (int)(LU_MAX_N / LU_PANEL_THREADS);   // rows of the panel per thread
 static_assert(LU_ROWS * LU_PANEL_THREADS >= LU_MAX_N, "the panel kernel holds every row of a panel");
 
 __global__ void lu_init(int32_t *info)

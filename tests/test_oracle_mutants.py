@@ -68,7 +68,7 @@ def _dft3d(x, sign):
 
 
 def _pins_pass(lib) -> bool:
-    """Return True iff every pin check accepts this build."""
+    """Return True iff every pin check accepts the oracle library `lib`."""
     ok = True
     # 1. transform vs the definition, both directions, non-cubic shape with radix 3
     x = inputs.uniform_grid((6, 16, 12), 21)
