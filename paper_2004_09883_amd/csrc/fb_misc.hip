@@ -149,29 +149,45 @@ hipError_t launch_evolve(int esize, const void *in, void *out, int64_t nx, int64
 
 // ---------------------------------------------------------------- checksum
 
-// 1024 threads; thread j loads x[(17 j) mod N]; pairwise tree in binary64.
-// Workgroup g sums grid g of `count` consecutive grids into out2[2g], out2[2g+1].
+// The 1024 samples x[(17 j) mod N] summed in binary64 by a fixed tree: level
+// h = 512, 256, ..., 1 adds sample j + h into sample j for j < h.  One
+// wavefront per grid: lane l holds samples l + 64 i (i < 16), so the levels
+// h >= 64 combine a lane's own values (i with i + h/64) and the levels h < 64
+// combine lane l with lane l + h (a lane exchange); lane 0 ends with the sum.
+// Every addition is the one the tree prescribes, so the result does not
+// depend on the launch shape.  Workgroup g sums grid g of `count` consecutive
+// grids into out2[2g], out2[2g+1].
 template <typename V>
-__global__ void __launch_bounds__(1024) checksum_kernel(const V *x, int64_t N, double *out2)
+__global__ void __launch_bounds__(64) checksum_kernel(const V *x, int64_t N, double *out2)
 {
-    __shared__ double sr[1024], si[1024];
-    const int j = threadIdx.x;
+    const int l = threadIdx.x;
     x += (int64_t)blockIdx.x * N;
     out2 += 2 * (int64_t)blockIdx.x;
-    const V v = x[(17 * (int64_t)j) % N];
-    sr[j] = (double)v.x;
-    si[j] = (double)v.y;
-    __syncthreads();
-    for (int h = 512; h > 0; h >>= 1) {
-        if (j < h) {
-            sr[j] += sr[j + h];
-            si[j] += si[j + h];
-        }
-        __syncthreads();
+    double sr[16], si[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const V v = x[(17 * (int64_t)(l + 64 * i)) % N];
+        sr[i] = (double)v.x;
+        si[i] = (double)v.y;
     }
-    if (j == 0) {
-        out2[0] = sr[0];
-        out2[1] = si[0];
+#pragma unroll
+    for (int h = 8; h > 0; h >>= 1) {   // tree levels 512 .. 64 within the lane
+#pragma unroll
+        for (int i = 0; i < h; i++) {
+            sr[i] += sr[i + h];
+            si[i] += si[i + h];
+        }
+    }
+    double r = sr[0], m = si[0];
+#pragma unroll
+    for (int h = 32; h > 0; h >>= 1) {   // levels 32 .. 1 across lanes
+        const double ro = __shfl_down(r, h), mo = __shfl_down(m, h);
+        r += ro;
+        m += mo;
+    }
+    if (l == 0) {
+        out2[0] = r;
+        out2[1] = m;
     }
 }
 
@@ -179,9 +195,9 @@ hipError_t launch_checksum(int esize, const void *x, int64_t N, double *out2, hi
 {
     if (count <= 0) return hipSuccess;
     if (esize == 16)
-        hipLaunchKernelGGL((checksum_kernel<double2>), dim3(count), dim3(1024), 0, st, (const double2 *)x, N, out2);
+        hipLaunchKernelGGL((checksum_kernel<double2>), dim3(count), dim3(64), 0, st, (const double2 *)x, N, out2);
     else
-        hipLaunchKernelGGL((checksum_kernel<float2>), dim3(count), dim3(1024), 0, st, (const float2 *)x, N, out2);
+        hipLaunchKernelGGL((checksum_kernel<float2>), dim3(count), dim3(64), 0, st, (const float2 *)x, N, out2);
     return hipGetLastError();
 }
 

@@ -156,6 +156,29 @@ def test_checksum(shape, dtype):
 
 
 @pytest.mark.parametrize("dtype", [fb.FB_C128, fb.FB_C64])
+@pytest.mark.parametrize("shape", [(32, 32, 32), (4, 4, 4), (3, 4, 8)])
+def test_checksum_summation_order(shape, dtype):
+    """The device sums the 1024 samples by a fixed binary64 tree (level h adds
+    sample j + h into sample j for j < h, h = 512 .. 1): equal bit for bit to
+    that tree evaluated here, whatever the grid size (small grids wrap the
+    sample index)."""
+    x = as_seen(inputs.uniform_grid(shape, 6), dtype)
+    plan = fb.Plan(*shape, dtype)
+    out2 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    fb.fb_checksum(plan, dev(x, dtype), out2)
+    flat = x.reshape(-1)
+    s = flat[(17 * np.arange(1024)) % flat.size].astype(np.complex128)
+    re, im = s.real.copy(), s.imag.copy()
+    h = 512
+    while h > 0:
+        re[:h] = re[:h] + re[h:2 * h]
+        im[:h] = im[:h] + im[h:2 * h]
+        h //= 2
+    got = out2.cpu().numpy()
+    assert got[0] == re[0] and got[1] == im[0]
+
+
+@pytest.mark.parametrize("dtype", [fb.FB_C128, fb.FB_C64])
 def test_fill_uniform_bitwise(dtype):
     shape = (8, 12, 48)
     plan = fb.Plan(*shape, dtype)
