@@ -41,9 +41,12 @@ namespace fb {
 __device__ __forceinline__ int64_t signed_k(int64_t i, int64_t n) { return (2 * i >= n) ? i - n : i; }
 
 template <typename V, int N, bool CONTIG, bool MX = false> struct PassCfg {
+    // complex128 tiles exchange real and imaginary parts in two rounds
+    static constexpr bool SPLIT = FB_SPLIT_EXCHANGE && std::is_same<V, double2>::value && N <= FB_SPLIT_MAX_N;
+    using LdsT = typename std::conditional<SPLIT, double, V>::type;   // LDS element
     static constexpr RadixPlan RP = radix_plan(N);
     static constexpr int T = threads_per_pencil(N);
-    static constexpr int P = pencils_per_wg(N, CONTIG, (int)sizeof(V), MX);
+    static constexpr int P = pencils_per_wg(N, CONTIG, (int)sizeof(V), MX, SPLIT);
     static constexpr int THREADS = P * T;
     static constexpr int M = regs_per_thread(N);
     static constexpr int LS = lds_pencil_stride(N);
@@ -594,7 +597,45 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                                                               MxMapContig<N / 16>{}, ldsp, ldsp);
             }
         } else {
-            if constexpr (s > 0) {
+            if constexpr (Cfg::SPLIT) {
+              if constexpr (s > 0) {
+                // exchange of a complex128 tile in two rounds through LDS rows
+                // of reals: real parts, then imaginary parts (a round's reads
+                // change only its own part of v, so the other part still holds
+                // the previous stage's outputs for the next round's writes)
+                constexpr int Rp = RP.r[s - 1];
+                constexpr int Nsp = RP.ns[s - 1];
+                constexpr int NBFp = N / Rp;
+                constexpr int Up = (NBFp + T - 1) / T;
+                R *rrow = (R *)lds + (active ? pp : 0) * LS;
+                static_for<0, 2>([&](auto hc) {
+                    constexpr int part = decltype(hc)::value;
+#pragma unroll
+                    for (int u = 0; active && u < Up; u++) {
+                        const int b = t + T * u;
+                        if (NBFp % T == 0 || b < NBFp) {
+                            const int idx = (b / Nsp) * Nsp * Rp + (b % Nsp);
+#pragma unroll
+                            for (int q = 0; q < Rp; q++)
+                                rrow[lds_pos(idx + q * Nsp)] = part ? v[u * Rp + q].y : v[u * Rp + q].x;
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int u = 0; active && u < U; u++) {
+                        const int b = t + T * u;
+                        if (NBF % T == 0 || b < NBF) {
+#pragma unroll
+                            for (int q = 0; q < Rr; q++) {
+                                if constexpr (part) v[u * Rr + q].y = rrow[lds_pos(b + q * NBF)];
+                                else v[u * Rr + q].x = rrow[lds_pos(b + q * NBF)];
+                            }
+                        }
+                    }
+                    __syncthreads();
+                });
+              }
+            } else if constexpr (s > 0) {
                 if constexpr (!MxStage<V, N, CONTIG, MX>::at(s - 1)) {
                     // exchange: write the previous stage's outputs
                     constexpr int Rp = RP.r[s - 1];
@@ -656,7 +697,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                 }
             }
         }
-        if constexpr (!CONTIG && !MX) {
+        if constexpr (!CONTIG && !MX && !Cfg::SPLIT) {
             if (a.otile) {   // uniform over the workgroup
                 store_tile_contiguous<V, N, CONTIG>(a, tile, tid, active, valid, t, row, lds, v);
                 return;
@@ -699,9 +740,9 @@ template <typename V, int N, bool CONTIG, bool MX>
 __global__ void __launch_bounds__((PassCfg<V, N, CONTIG, MX>::THREADS)) FB_OCCUPANCY fft_pass(PassArgs a)
 {
     using Cfg = PassCfg<V, N, CONTIG, MX>;
-    __shared__ V lds[Cfg::P * Cfg::LS];
+    __shared__ typename Cfg::LdsT lds[Cfg::P * Cfg::LS];
     __shared__ real_t<V> gtab[CONTIG ? N : 1];
-    pass_tile<V, N, CONTIG, MX>(a, blockIdx.x, threadIdx.x, lds, gtab);
+    pass_tile<V, N, CONTIG, MX>(a, blockIdx.x, threadIdx.x, (V *)lds, gtab);
 }
 
 // Contiguous evolve pass with several outputs: the tile's spectrum is read
@@ -711,9 +752,9 @@ template <typename V, int N, bool MX>
 __global__ void __launch_bounds__((PassCfg<V, N, true, MX>::THREADS)) FB_OCCUPANCY fft_pass_multi(PassArgs a)
 {
     using Cfg = PassCfg<V, N, true, MX>;
-    __shared__ V lds[Cfg::P * Cfg::LS];
+    __shared__ typename Cfg::LdsT lds[Cfg::P * Cfg::LS];
     __shared__ real_t<V> gtab[N];
-    pass_tile<V, N, true, MX, true>(a, blockIdx.x, threadIdx.x, lds, gtab);
+    pass_tile<V, N, true, MX, true>(a, blockIdx.x, threadIdx.x, (V *)lds, gtab);
 }
 
 }  // namespace fb

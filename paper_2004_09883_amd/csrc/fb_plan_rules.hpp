@@ -85,6 +85,21 @@ constexpr int lds_pencil_stride(int n)
 #ifndef FB_LDS_CONTIG_MX_KB
 #define FB_LDS_CONTIG_MX_KB 20   // contiguous complex64 matrix-core passes
 #endif
+// Complex128 vector-unit passes exchange real and imaginary parts through
+// LDS one after the other (FB_SPLIT_EXCHANGE = 1): half the LDS per tile, so
+// more tiles fit a CU; their budgets are then FB_LDS_SPLIT_*_KB.
+#ifndef FB_SPLIT_EXCHANGE
+#define FB_SPLIT_EXCHANGE 1
+#endif
+#ifndef FB_SPLIT_MAX_N
+#define FB_SPLIT_MAX_N 256   // longer passes keep the one-round exchange
+#endif
+#ifndef FB_LDS_SPLIT_CONTIG_KB
+#define FB_LDS_SPLIT_CONTIG_KB 10
+#endif
+#ifndef FB_LDS_SPLIT_STRIDED_KB
+#define FB_LDS_SPLIT_STRIDED_KB 36
+#endif
 #ifndef FB_LDS_STRIDED_KB
 #define FB_LDS_STRIDED_KB 72
 #endif
@@ -108,9 +123,13 @@ constexpr int lds_budget_bytes(bool contig, int esize, bool mx = false)
 
 constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
 
-constexpr bool pencils_fit(int P, int n, bool contig, int esize, bool mx = false)
+// split: the tile's LDS holds one real part per element (8 bytes) at a time
+constexpr bool pencils_fit(int P, int n, bool contig, int esize, bool mx = false, bool split = false)
 {
-    return P * threads_per_pencil(n) <= 1024 && P * lds_pencil_stride(n) * esize <= lds_budget_bytes(contig, esize, mx);
+    const int elem = split ? 8 : esize;
+    const int budget = split ? (contig ? FB_LDS_SPLIT_CONTIG_KB : FB_LDS_SPLIT_STRIDED_KB) * 1024
+                             : lds_budget_bytes(contig, esize, mx);
+    return P * threads_per_pencil(n) <= 1024 && P * lds_pencil_stride(n) * elem <= budget;
 }
 
 // Pencils per workgroup.  Contiguous passes aim for 256 threads; strided
@@ -121,7 +140,7 @@ constexpr bool pencils_fit(int P, int n, bool contig, int esize, bool mx = false
 // matrix-core pass (mx) takes the budget of its own kind only where the tile
 // stays whole wavefronts (which the matrix-core stages need); otherwise that
 // of the vector-unit pass.
-constexpr int pencils_per_wg_b(int n, bool contig, int esize, bool mx)
+constexpr int pencils_per_wg_b(int n, bool contig, int esize, bool mx, bool split)
 {
     const int T = threads_per_pencil(n);
     int P = contig ? (FB_CONTIG_THREADS / T > 0 ? FB_CONTIG_THREADS / T : 1)
@@ -131,18 +150,18 @@ constexpr int pencils_per_wg_b(int n, bool contig, int esize, bool mx)
     if (P % m) {
         const int down = (P / m) * m, up = down + m;
         if (down > 0) P = down;
-        else if (pencils_fit(up, n, contig, esize, mx)) P = up;
+        else if (pencils_fit(up, n, contig, esize, mx, split)) P = up;
     }
-    while (P > 1 && !pencils_fit(P, n, contig, esize, mx)) P /= 2;
+    while (P > 1 && !pencils_fit(P, n, contig, esize, mx, split)) P /= 2;
     return P;
 }
-constexpr int pencils_per_wg(int n, bool contig, int esize, bool mx = false)
+constexpr int pencils_per_wg(int n, bool contig, int esize, bool mx = false, bool split = false)
 {
     if (mx) {
-        const int P = pencils_per_wg_b(n, contig, esize, true);
+        const int P = pencils_per_wg_b(n, contig, esize, true, split);
         if ((P * threads_per_pencil(n)) % 64 == 0) return P;
     }
-    return pencils_per_wg_b(n, contig, esize, false);
+    return pencils_per_wg_b(n, contig, esize, false, split);
 }
 
 }  // namespace fb
