@@ -356,6 +356,83 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// The same update on the binary64 matrix cores (FB_LU_MFMA = 1):
+// v_mfma_f64_16x16x4f64 computes D = A B + C for a 16 x 4 block A, a 4 x 16
+// block B and a 16 x 16 block C; lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and holds D[4 r + l / 16][l % 16] in its register r < 4
+// (rows interleaved over the four 16-lane groups; checked on the device with
+// known operands).  Each wave
+// of the 64 x 64 tile computes a 32 x 32 quadrant as 2 x 2 such blocks over
+// the panel's columns in steps of 4, with A = -L21 so that the accumulator
+// starts from A22 and ends at A22 - L21 U12.
+#ifndef FB_LU_MFMA
+#define FB_LU_MFMA 1
+#endif
+typedef double lu_d4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256)
+    lu_gemm_mfma(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb)
+{
+    __shared__ double Ls[LU_TILE][LU_NB + 1];
+    __shared__ double Us[LU_NB][LU_TILE + 4];
+    const int64_t s = k + nb;   // first row and column of A22
+    const int64_t r0 = s + (int64_t)blockIdx.y * LU_TILE, c0 = s + (int64_t)blockIdx.x * LU_TILE;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < LU_TILE * LU_NB; idx += 256) {
+        const int i = idx / LU_NB, j = idx % LU_NB;
+        Ls[i][j] = (r0 + i < n && j < nb) ? -a[(r0 + i) * lda + k + j] : 0.0;
+    }
+    for (int idx = tid; idx < LU_NB * LU_TILE; idx += 256) {
+        const int j = idx / LU_TILE, c = idx % LU_TILE;
+        Us[j][c] = (c0 + c < n && j < nb) ? a[(k + j) * lda + c0 + c] : 0.0;
+    }
+    const int wave = tid >> 6, lane = tid & 63;
+    const int qr = 32 * (wave >> 1), qc = 32 * (wave & 1);   // the wave's quadrant of the tile
+    const int li = lane & 15, lk = lane >> 4;
+    lu_d4 acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; bi++) {
+#pragma unroll
+        for (int bj = 0; bj < 2; bj++) {
+            const int64_t cc = c0 + qc + 16 * bj + li;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int64_t rr = r0 + qr + 16 * bi + 4 * r + lk;
+                acc[bi][bj][r] = (rr < n && cc < n) ? a[rr * lda + cc] : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < LU_NB; k4 += 4) {
+        if (k4 < nb) {   // uniform; columns nb .. k4 + 3 of the tiles are zero
+            double av[2], bv[2];
+#pragma unroll
+            for (int bi = 0; bi < 2; bi++) av[bi] = Ls[qr + 16 * bi + li][k4 + lk];
+#pragma unroll
+            for (int bj = 0; bj < 2; bj++) bv[bj] = Us[k4 + lk][qc + 16 * bj + li];
+#pragma unroll
+            for (int bi = 0; bi < 2; bi++) {
+#pragma unroll
+                for (int bj = 0; bj < 2; bj++)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; bi++) {
+#pragma unroll
+        for (int bj = 0; bj < 2; bj++) {
+            const int64_t cc = c0 + qc + 16 * bj + li;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int64_t rr = r0 + qr + 16 * bi + 4 * r + lk;
+                if (rr < n && cc < n) a[rr * lda + cc] = acc[bi][bj][r];
+            }
+        }
+    }
+}
+
 hipError_t launch_lu(double *a, int64_t n, int64_t lda, int32_t *ipiv, int32_t *info, hipStream_t st)
 {
     hipLaunchKernelGGL(lu_init, dim3(1), dim3(64), 0, st, info);
@@ -369,7 +446,8 @@ hipError_t launch_lu(double *a, int64_t n, int64_t lda, int32_t *ipiv, int32_t *
         const int64_t rest = n - k - nb;
         if (rest > 0) {
             const unsigned t = (unsigned)((rest + LU_TILE - 1) / LU_TILE);
-            hipLaunchKernelGGL(lu_gemm, dim3(t, t), dim3(256), 0, st, a, n, lda, k, nb);
+            if (FB_LU_MFMA) hipLaunchKernelGGL(lu_gemm_mfma, dim3(t, t), dim3(256), 0, st, a, n, lda, k, nb);
+            else hipLaunchKernelGGL(lu_gemm, dim3(t, t), dim3(256), 0, st, a, n, lda, k, nb);
         }
         e = hipGetLastError();
     }
