@@ -11,11 +11,11 @@
 //   lu_swap_trsm  applies the panel's row swaps, in order, to every column
 //             outside the panel, then U12 = L11^-1 A12 for the columns right
 //             of it (one thread per column, L11 in LDS);
-//   lu_gemm   A22 -= L21 U12 on 64 x 64 tiles (L21 and U12 tiles in LDS).
+//   lu_gemm_mfma  A22 -= L21 U12 on 64 x 64 tiles (L21 and U12 tiles in
+//             LDS) on the binary64 matrix cores (lu_gemm: the same on the
+//             vector units, FB_LU_MFMA = 0).
 // Every element receives its updates in increasing column order j, as in
-// unblocked elimination.  On gfx950 the dense binary64 matrix-core rate
-// equals the vector rate, and the rank-16 update is bound by memory traffic,
-// so the update uses vector FMAs.
+// unblocked elimination (both update kernels give the same bits).
 #include <hip/hip_runtime.h>
 
 #include "fb_device.hpp"
@@ -361,10 +361,9 @@ __global__ void __launch_bounds__(256)
 // block B and a 16 x 16 block C; lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16] and holds D[4 r + l / 16][l % 16] in its register r < 4
 // (rows interleaved over the four 16-lane groups; checked on the device with
-// known operands).  Each wave
-// of the 64 x 64 tile computes a 32 x 32 quadrant as 2 x 2 such blocks over
-// the panel's columns in steps of 4, with A = -L21 so that the accumulator
-// starts from A22 and ends at A22 - L21 U12.
+// known operands).  Each wave of the 64 x 64 tile computes a 32 x 32
+// quadrant as 2 x 2 such blocks over the panel's columns in steps of 4, with
+// A = -L21 so that the accumulator starts from A22 and ends at A22 - L21 U12.
 #ifndef FB_LU_MFMA
 #define FB_LU_MFMA 1
 #endif
