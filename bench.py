@@ -19,6 +19,7 @@ import argparse
 import hashlib
 import json
 import math
+import re
 import os
 import sys
 import time
@@ -222,7 +223,10 @@ def forms_section(torch, fb, reps: int = 50, steps: int = 10) -> dict:
                "hbm_roofline_frac": round(b_alg / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
                "step_ms": round(ms_step, 4),
                "step_hbm_roofline_frac": round(b_alg / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
-               "model_bytes": b_alg, "passes": passes}
+               "model_bytes": b_alg,
+               # the compulsory minimum: the grid read once and written once
+               "compulsory_roofline_frac": round(2 * esize * n / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+               "passes": passes}
         if name == "c128":
             ref["u"] = u.clone()
             ref["x"] = xt.clone()
@@ -264,9 +268,13 @@ def batched_section(torch, fb, reps: int = 10) -> dict:
     for n in lens:
         model_bytes += (2 if n <= 4096 else 4) * 8 * n
     model_bytes += 64 * 4 * 8 * 512 * 512
+    # launches per execution: one per (length, pass) group, or one per phase
+    # of the persistent mode (the second phase only when a transform needs it)
+    m = re.search(r"tiles=(\d+)\+(\d+)", batch.description)
+    phases = 1 + (1 if m and int(m.group(2)) > 0 else 0)
     out = {"workload": "4096 1D complex64 FFTs, lengths uniform over {2^k, 3*2^k: 8<=k<=16} (seed 3), plus 64 "
                        "2D 512x512; uniform [-1,1) inputs", "transforms": 4096 + 64, "elements": batch.elements,
-           "model_bytes": model_bytes, "per_group_launches": batch.launches}
+           "model_bytes": model_bytes, "launches": {"per_group_launches": batch.launches, "persistent": phases}}
     for mode, persistent in (("per_group_launches", False), ("persistent", True)):
         for _ in range(2):
             fb.fb_batch_exec(batch, x, y, wsp, fb.FB_FORWARD, persistent)
