@@ -84,7 +84,9 @@ def test_single_axis_pass(axis, n, dtype):
 # ---------------------------------------------------------------- whole 3D transforms
 
 SHAPES_3D = [(64, 64, 64), (32, 48, 96), (12, 96, 24), (3, 6, 12), (1, 1, 1), (1, 1, 4096), (4096, 1, 2),
-             (2, 4096, 1), (128, 256, 512), (256, 256, 128)]
+             (2, 4096, 1), (128, 256, 512), (256, 256, 128),
+             # pencil counts that leave a part-filled last tile on every axis
+             (3, 3, 256), (3, 256, 3), (256, 3, 3), (6, 3, 96)]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
