@@ -306,6 +306,15 @@ def test_block_strong_decay_and_nz1_fallback():
     check_block((24, 12, 48), fb.FB_C128, seed=8, alpha=1e-3, steps=3)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("shape", [(3, 3, 256), (3, 256, 3), (6, 3, 96)])
+def test_block_part_filled_tiles(shape, dtype):
+    """The fused step (evolution in the first inverse pass) where the last
+    tile of a pass holds fewer pencils than the others."""
+    print(f"block shape={shape} dtype={dtype}", flush=True)
+    check_block(shape, dtype, seed=4, alpha=1e-4, steps=3)
+
+
 @pytest.mark.parametrize("dtype", [fb.FB_C64, fb.FB_C64_SPLITBF16])
 def test_block_c64(dtype):
     check_block((64, 64, 64), dtype, seed=1, alpha=1e-6, steps=6)
