@@ -147,6 +147,31 @@ def _ptr(x) -> int:
     return int(x.data_ptr())
 
 
+def _check_sums(t, need: int, name: str, allow_none: bool):
+    """A checksum destination: a contiguous float64 device tensor of at least
+    `need` values (or a raw device address, or None where the call allows
+    it).  Checked here because the C side can only see the pointer."""
+    if t is None:
+        if allow_none:
+            return
+        raise FbError(FB_ERR_INVALID_ARG, f"{name} is required")
+    if isinstance(t, int):
+        if t == 0 and not allow_none:
+            raise FbError(FB_ERR_INVALID_ARG, f"{name} is NULL")
+        return
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise FbError(FB_ERR_INVALID_ARG, f"{name} must be a float64 device tensor")
+    if t.dtype != torch.float64:
+        raise FbError(FB_ERR_DTYPE, f"{name} is {t.dtype}, needs torch.float64")
+    if t.numel() < need:
+        raise FbError(FB_ERR_INVALID_ARG, f"{name} holds {t.numel()} values, needs at least {need}")
+    if not t.is_contiguous():
+        raise FbError(FB_ERR_INVALID_ARG, f"{name} must be contiguous")
+    if not t.is_cuda:
+        raise FbError(FB_ERR_INVALID_ARG, f"{name} must be a device tensor")
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -259,12 +284,14 @@ def fb_spectral_evolve(plan: Plan, u, alpha: float, t: float, stream=None):
 def fb_checksum(plan: Plan, x, out2, stream=None):
     """out2: a float64 device tensor with at least 2 elements (or an address)."""
     plan.check_tensor(x, "x")
+    _check_sums(out2, 2, "out2", allow_none=False)
     _check(load().fb_checksum(plan.handle, _ptr(x), _ptr(out2), _stream(stream)))
 
 
 def fb_spectral_step(plan: Plan, uhat0, x_out, alpha: float, t: float, out2=None, stream=None):
     plan.check_tensor(uhat0, "uhat0")
     plan.check_tensor(x_out, "x_out")
+    _check_sums(out2, 2, "out2", allow_none=True)
     _check(load().fb_spectral_step(plan.handle, _ptr(uhat0), _ptr(x_out), float(alpha), float(t),
                                    _ptr(out2), _stream(stream)))
 
@@ -310,6 +337,7 @@ def fb_spectral_steps(plan: Plan, uhat0, x_out, alpha: float, ts, sums=None, str
                                        or x_out.dtype != plan.torch_dtype or not x_out.is_cuda):
         raise FbError(FB_ERR_INVALID_ARG, f"x_out must be a contiguous {plan.torch_dtype} device tensor of "
                                           f"{len(ts)} grids")
+    _check_sums(sums, 2 * len(ts), "sums", allow_none=True)
     arr = (ctypes.c_double * max(1, len(ts)))(*ts)
     _check(load().fb_spectral_steps(plan.handle, _ptr(uhat0), _ptr(x_out), float(alpha), arr, len(ts), _ptr(sums),
                                     _stream(stream)))

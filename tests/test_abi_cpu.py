@@ -122,3 +122,81 @@ def test_lu_and_steps_reject_before_device():
     assert lib.fb_spectral_steps(None, 16, 16, 1e-6, ts, 2, None, None) == fb.FB_ERR_INVALID_ARG
     assert lib.fb_fft3d_exec_host(None, 16, 16, -1) == fb.FB_ERR_INVALID_ARG
     assert lib.fb_fft3d_forward_uniform(None, 1, 16, None) == fb.FB_ERR_INVALID_ARG
+
+
+class _RecordingLib:
+    """Stands in for libfb: records every entry point called."""
+
+    def __init__(self):
+        self.calls = []
+
+    def __getattr__(self, name):
+        def f(*args):
+            self.calls.append(name)
+            return 0
+        return f
+
+
+class _FakePlan:
+    """A plan whose grid checks pass, so that only the checksum buffers are
+    judged (no device here to make a real plan)."""
+    shape = (4, 4, 4)
+    handle = 1
+
+    def check_tensor(self, x, name="x"):
+        return None
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.complex128
+
+
+def _bad_sums():
+    import torch
+    return [
+        ("cpu tensor", torch.zeros(2, dtype=torch.float64), fb.FB_ERR_INVALID_ARG),
+        ("float32", torch.zeros(2, dtype=torch.float32), fb.FB_ERR_DTYPE),
+        ("too small", torch.zeros(1, dtype=torch.float64), None),
+        ("not contiguous", torch.zeros(4, dtype=torch.float64)[::2], None),
+        ("not a tensor", [0.0, 0.0], fb.FB_ERR_INVALID_ARG),
+    ]
+
+
+@pytest.mark.parametrize("call", ["fb_checksum", "fb_spectral_step", "fb_spectral_steps"])
+def test_binding_rejects_bad_checksum_buffers_before_any_call(monkeypatch, call):
+    """A checksum destination that is on the host, of the wrong dtype, too
+    small or strided raises FbError in the binding and nothing reaches the
+    library (the kernel would otherwise write through a host pointer or past
+    the allocation)."""
+    rec = _RecordingLib()
+    monkeypatch.setattr(fb, "_lib", rec)
+    plan = _FakePlan()
+    for label, sums, code in _bad_sums():
+        with pytest.raises(fb.FbError) as e:
+            if call == "fb_checksum":
+                fb.fb_checksum(plan, 0, sums, stream=0)
+            elif call == "fb_spectral_step":
+                fb.fb_spectral_step(plan, 0, 0, 1e-6, 1.0, sums, stream=0)
+            else:
+                fb.fb_spectral_steps(plan, 0, 0, 1e-6, [1.0], sums, stream=0)
+        if code is not None:
+            assert e.value.code == code, label
+        assert rec.calls == [], (label, rec.calls)
+    if call == "fb_checksum":
+        with pytest.raises(fb.FbError):
+            fb.fb_checksum(plan, 0, None, stream=0)
+    assert rec.calls == []
+
+
+def test_binding_steps_sums_sized_for_every_step(monkeypatch):
+    """fb_spectral_steps needs 2 values per step: a buffer of 2 values for
+    3 steps is rejected before the call."""
+    import torch
+    rec = _RecordingLib()
+    monkeypatch.setattr(fb, "_lib", rec)
+    with pytest.raises(fb.FbError) as e:
+        fb.fb_spectral_steps(_FakePlan(), 0, 0, 1e-6, [1.0, 2.0, 3.0], torch.zeros(2, dtype=torch.float64),
+                             stream=0)
+    assert "at least 6" in e.value.msg
+    assert rec.calls == []
