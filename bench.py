@@ -1,17 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the 3D FFT spectral block on one MI355X.
 
-One step = one whole spectral block of the 256 x 256 x 128 complex128
-workload: the forward 3D FFT of a seeded uniform grid, then for t = 1..20
-the fused evolve (alpha = 1e-6) + inverse 3D FFT + checksum, all through the
-C ABI (libfb.so).  Inputs are generated on the device before the timed
-region and stay resident in HBM.
+One step = one whole spectral block of the 512 x 256 x 256 complex128
+workload (binary64): the forward 3D FFT of a seeded N(0,1) grid (Box-Muller,
+seed 2), then for t = 1..10 the fused evolve (alpha = 1e-6) + inverse 3D FFT
++ stride-17 checksum, all through the C ABI (libfb.so).  The grid is 512 MiB,
+twice the 256 MB last-level cache, so the passes stream from HBM.  Inputs are
+copied to the device before the timed region and stay resident in HBM.
 
 Prints one JSON line with the throughput (GFLOP/s, 5 N log2 N per transform),
-the roofline of the dominant kernel (per-launch HIP events recorded by the
-library on the stream the kernels run on), the CPU oracle timed on a bounded
-sample of the same workload, and the forms of the 512 x 256 x 256 grid
-(complex128 vs complex64 forward FFT).
+the roofline of the dominant kernel (HIP events on the stream its launches
+run on), the CPU oracle timed on the same workload, the complex64 and
+split-bf16 forms of the same block, and secondary figures (the 256 x 256 x
+128 block, whose 128 MiB grid stays in the last-level cache, the batched and
+served forms, the paper's 2048 x 2048 transform and the LU block).
 """
 from __future__ import annotations
 
@@ -29,10 +31,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FFT GFLOP/s (5NlogN) & %HBM roofline; served p50/p99 latency; FP32 vs FP64"
 HBM_PEAK_GBS = 8000.0
-SHAPE = (256, 256, 128)
+SHAPE = (512, 256, 256)        # the headline block
 ALPHA = 1e-6
-T_STEPS = 20
-SEED = 1
+T_STEPS = 10
+SEED = 2                       # N(0,1) entries by Box-Muller
+CACHE_SHAPE = (256, 256, 128)  # secondary block: the grid fits the last-level cache
+CACHE_STEPS = 20
+CACHE_SEED = 1                 # uniform [-1, 1) entries
+HEADLINE_SCHEDULE = "per_step"  # fb_spectral_step per step ("fused_steps": fb_spectral_steps)
 KERNEL_SOURCES = ["paper_2004_09883_amd/csrc/fb_pass.hpp", "paper_2004_09883_amd/csrc/fb_device.hpp",
                   "paper_2004_09883_amd/csrc/fb_plan_rules.hpp", "paper_2004_09883_amd/csrc/fb_pass_inst.hpp",
                   "paper_2004_09883_amd/csrc/fb_mfma.hpp", "paper_2004_09883_amd/csrc/fb_internal.hpp"]
@@ -51,9 +57,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on different kernel sources."""
+def traffic_for(kernel: str, shape):
+    """HBM bytes per launch of `kernel` on a grid of `shape` from the
+    committed rocprofv3 counter summary, or None when it is missing or was
+    taken on different kernel sources."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     try:
         with open(path) as f:
@@ -62,7 +69,8 @@ def traffic_for(kernel: str):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    rec = d.get("kernels", {}).get(kernel)
+    key = "x".join(str(v) for v in shape)
+    rec = d.get("workloads", {}).get(key, {}).get("kernels", {}).get(kernel)
     return None if rec is None else rec.get("hbm_bytes_per_launch")
 
 
@@ -122,38 +130,44 @@ def small_block_section(torch, fb, reps: int = 20) -> dict:
             "launches": 3 + steps * 4}
 
 
-def cpu_baseline(budget_steps: int = 10) -> dict:
-    """The oracle (plain C, binary64) on the host cores: forward 3D FFT plus
-    `budget_steps` of the 20 evolve/inverse/checksum steps of the same
-    workload, scaled to GFLOP/s."""
-    import numpy as np  # noqa: F401
-
+def cpu_baseline(runs: int = 3, sample_steps: int = 3, host_x0=None) -> dict:
+    """The oracle (plain C, binary64, OpenMP over pencils) on the host cores,
+    on a bounded sample of the headline workload: the forward 3D FFT of the
+    512 x 256 x 256 N(0,1) grid plus `sample_steps` of its 10
+    evolve/inverse/checksum steps, median of `runs`, scaled to GFLOP/s; and
+    one forward transform on one thread."""
     import oracle
     from paper_2004_09883_amd import inputs
 
-    x0 = inputs.uniform_grid(SHAPE, SEED)
-    t0 = time.perf_counter()
-    X0 = oracle.fft3d(x0, -1)
-    for t in range(1, budget_steps + 1):
-        xt = oracle.fft3d(oracle.evolve(X0, ALPHA, t), +1)
-        oracle.checksum(xt)
-    dt = time.perf_counter() - t0
-    # the same oracle on one core: one forward transform
+    x0 = host_x0 if host_x0 is not None else inputs.gaussian_grid(SHAPE, SEED)
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        X0 = oracle.fft3d(x0, -1)
+        for t in range(1, sample_steps + 1):
+            xt = oracle.fft3d(oracle.evolve(X0, ALPHA, t), +1)
+            oracle.checksum(xt)
+            del xt
+        times.append(time.perf_counter() - t0)
+        del X0
+    dt = sorted(times)[len(times) // 2]
     nthreads = oracle.threads()
     oracle.set_threads(1)
     t1 = time.perf_counter()
     oracle.fft3d(x0, -1)
     dt1 = time.perf_counter() - t1
     oracle.set_threads(nthreads)
-    return {"value": round((1 + budget_steps) * flops_fft(SHAPE) / dt / 1e9, 3),
+    return {"value": round((1 + sample_steps) * flops_fft(SHAPE) / dt / 1e9, 3),
             "value_1_thread": round(flops_fft(SHAPE) / dt1 / 1e9, 3), "unit": "GFLOP/s",
-            "cores": oracle.threads(), "cpu_model": cpu_model(), "kind": "oracle",
-            "sample": f"forward FFT + {budget_steps} of the {T_STEPS} evolve/inverse/checksum steps of the "
-                      f"{SHAPE[0]}x{SHAPE[1]}x{SHAPE[2]} complex128 block ({dt:.2f} s wall); one-thread value: one "
-                      f"forward FFT ({dt1:.2f} s)"}
+            "cores": nthreads, "cpu_model": cpu_model(), "nproc": os.cpu_count(), "kind": "oracle",
+            "sample_s_median": round(dt, 3), "sample_s_runs": [round(v, 3) for v in times],
+            "sample": f"forward FFT + {sample_steps} of the {T_STEPS} evolve/inverse/checksum steps of the "
+                      f"{SHAPE[0]}x{SHAPE[1]}x{SHAPE[2]} complex128 block (same input), median of {runs} runs "
+                      f"on {nthreads} threads; one-thread value: one forward FFT ({dt1:.2f} s)"}
 
 
-def forms_section(torch, fb, reps: int = 50, steps: int = 10) -> dict:
+def forms_section(torch, fb, reps: int = 50, steps: int = 10, host_x0=None, block_ms_c128=None,
+                  block_reps: int = 10) -> dict:
     """512 x 256 x 256 grid of N(0,1) entries (Box-Muller, seed 2; the
     complex64 forms get the values rounded to complex64): per form the
     forward 3D FFT and one fused spectral step (evolve + inverse FFT +
@@ -164,7 +178,9 @@ def forms_section(torch, fb, reps: int = 50, steps: int = 10) -> dict:
 
     shape = (512, 256, 256)
     n = math.prod(shape)
-    host = torch.from_numpy(inputs.gaussian_grid(shape, 2))
+    if host_x0 is None:
+        host_x0 = inputs.gaussian_grid(shape, 2)
+    host = torch.from_numpy(host_x0)
     out = {}
     ref = {}
 
@@ -236,13 +252,30 @@ def forms_section(torch, fb, reps: int = 50, steps: int = 10) -> dict:
         out[name] = rec
         del x, u, xt, plan
         torch.cuda.empty_cache()
+    # the whole block of each form (forward + `steps` fused steps, per-step
+    # schedule, HIP graph replay): the speedup on the workload itself
+    for name, dt in (("c128", fb.FB_C128), ("c64", fb.FB_C64), ("c64_splitbf16", fb.FB_C64_SPLITBF16)):
+        if name == "c128" and block_ms_c128 is not None:
+            out[name]["block_ms"] = round(block_ms_c128, 4)
+            continue
+        blk = SpectralBlock(torch, fb, shape, dt, steps, host_x0=host_x0)
+        for _ in range(2):
+            blk.run()
+        tb = time_replays(torch, blk.run, warmup=2, reps=block_reps)
+        tb.pop("graph")
+        out[name]["block_ms"] = round(tb["ms"], 4)
+        del blk
+        torch.cuda.empty_cache()
+    for k in ("c64", "c64_splitbf16"):
+        out[k + "_block_speedup_vs_c128"] = round(out["c128"]["block_ms"] / out[k]["block_ms"], 3)
     out["c64_speedup_vs_c128"] = round(out["c128"]["forward_ms"] / out["c64"]["forward_ms"], 3)
     out["c64_splitbf16_speedup_vs_c128"] = round(out["c128"]["forward_ms"] / out["c64_splitbf16"]["forward_ms"], 3)
     for k in ("c64", "c64_splitbf16"):
         out[k + "_in_place_speedup_vs_c128"] = round(out["c128"]["forward_in_place_ms"] / out[k]["forward_in_place_ms"],
                                                      3)
-    out["workload"] = ("512x256x256 grid, N(0,1) entries (Box-Muller, seed 2): forward 3D FFT (3 pencil passes) "
-                       "and one spectral step at t=%d, alpha=1e-6" % steps)
+    out["workload"] = ("512x256x256 grid, N(0,1) entries (Box-Muller, seed 2): forward 3D FFT (3 pencil passes), "
+                       "one spectral step at t=%d, and the whole block (forward + %d fused steps, alpha=1e-6)"
+                       % (steps, steps))
     del ref
     torch.cuda.empty_cache()
     return out
@@ -391,6 +424,165 @@ def copy_reference(torch, nbytes: int = 1 << 29, reps: int = 20) -> dict:
     return {"bytes_moved": 2 * nbytes, "ms": round(ms, 4), "gbs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
+class SpectralBlock:
+    """One spectral block on the device: the forward 3D FFT of x0, then for
+    t = 1..steps the fused evolve + inverse FFT + checksum.  schedule
+    "per_step": fb_spectral_step into one output grid per step;
+    "fused_steps": fb_spectral_steps, chunks of up to 8 steps sharing their
+    first inverse pass, one output grid per step."""
+
+    def __init__(self, torch, fb, shape, dtype, steps, host_x0=None, seed=None, schedule="per_step"):
+        self.fb, self.shape, self.steps, self.schedule = fb, tuple(shape), steps, schedule
+        self.plan = fb.Plan(*shape, dtype)
+        self.x0 = torch.empty(shape, dtype=self.plan.torch_dtype, device="cuda")
+        if host_x0 is not None:
+            self.x0.copy_(torch.from_numpy(host_x0).to(self.plan.torch_dtype))
+        else:
+            fb.fb_fill_uniform(self.plan, self.x0, seed)
+        self.u0 = torch.empty_like(self.x0)
+        self.sums = torch.zeros((steps, 2), dtype=torch.float64, device="cuda")
+        if schedule == "per_step":
+            self.out = torch.empty_like(self.x0)
+        else:
+            self.out = torch.empty((steps,) + self.shape, dtype=self.plan.torch_dtype, device="cuda")
+        self.ts = [float(t) for t in range(1, steps + 1)]
+
+    def run(self):
+        fb = self.fb
+        fb.fb_fft3d_exec(self.plan, self.x0, self.u0, fb.FB_FORWARD)
+        if self.schedule == "per_step":
+            for j, t in enumerate(self.ts):
+                fb.fb_spectral_step(self.plan, self.u0, self.out, ALPHA, t, self.sums[j])
+        else:
+            fb.fb_spectral_steps(self.plan, self.u0, self.out, ALPHA, self.ts, self.sums)
+
+    def launches(self) -> int:
+        """Kernel launches per block: 3 forward passes, then per step 3
+        passes and a checksum (per_step), or per chunk of up to 8 steps one
+        multi-output pass, the y and x passes over the chunk's grids and one
+        checksum launch (fused_steps)."""
+        if self.schedule == "per_step":
+            return 3 + 4 * self.steps
+        return 3 + 4 * ((self.steps + 7) // 8)
+
+    def flops(self) -> float:
+        return (1 + self.steps) * flops_fft(self.shape)
+
+
+def time_replays(torch, fn, warmup: int, reps: int, graph: bool = True):
+    """Capture fn() in a HIP graph (unless graph is False), replay it `warmup`
+    times, then time `reps` replays back to back between HIP events on the
+    launch stream (one event after each replay).  Returns the mean over the
+    reps (first to last event), the per-replay median and minimum, the wall
+    time and the graph (kept alive by the caller while it is used)."""
+    g = None
+    run = fn
+    if graph:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        run = g.replay
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    t_wall = time.perf_counter()
+    ev[0].record()
+    for r in range(reps):
+        run()
+        ev[r + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    each = sorted(ev[r].elapsed_time(ev[r + 1]) for r in range(reps))
+    return {"ms": ev[0].elapsed_time(ev[reps]) / reps, "ms_median": each[len(each) // 2], "ms_min": each[0],
+            "wall_s": wall, "graph": g}
+
+
+def axis_kernels(fb, plan, buf) -> dict:
+    """Which pencil-pass kernel each single-axis call launches: {kernel name:
+    axis mask} (bit 0 z, bit 1 y, bit 2 x), read from the library's own
+    launch records."""
+    import torch
+    out = {}
+    for mask in (1, 2, 4):
+        fb.fb_profile_enable(True)
+        fb.fb_fft3d_exec_axes(plan, buf, buf, fb.FB_INVERSE, mask)
+        torch.cuda.synchronize()
+        rep = fb.fb_profile_report()
+        fb.fb_profile_enable(False)
+        for k in rep:
+            if k["kernel"].startswith("fft_pass"):
+                out.setdefault(k["kernel"], mask)
+    return out
+
+
+def dominant_kernel_roofline(torch, fb, blk, prof, reps: int = 20) -> dict:
+    """Roofline of the block's dominant kernel (largest total time among the
+    pencil passes in the library's launch records): its algorithmic bytes
+    per launch (the grid read once and written once, 2 E N) over its
+    average duration, timed as `reps` launches of that pass alone captured
+    in a HIP graph, replayed once, then replayed between two HIP events on
+    the launch stream."""
+    passes = [k for k in prof if k["kernel"].startswith("fft_pass")]
+    dom = max(passes, key=lambda k: k["total_ms"])
+    buf = blk.out if blk.schedule == "per_step" else blk.out[0]
+    masks = axis_kernels(fb, blk.plan, buf)
+    mask = masks.get(dom["kernel"])
+    rec = {"bound": "hbm", "kernel": dom["kernel"], "bytes_per_launch": dom["bytes_per_launch"],
+           "avg_launch_ms_event_bracketed": round(dom["avg_ms"], 5)}
+    if mask is None:
+        dom_ms = dom["avg_ms"]
+        rec["timing"] = "per-launch HIP events of the library's launch records"
+    else:
+        def alone():
+            for _ in range(reps):
+                fb.fb_fft3d_exec_axes(blk.plan, buf, buf, fb.FB_INVERSE, mask)
+        t = time_replays(torch, alone, warmup=1, reps=1)
+        dom_ms = t["ms"] / reps
+        del t
+        rec["timing"] = f"{reps} launches of the pass alone (axis mask {mask}) in a HIP graph, HIP events on the launch stream"
+    achieved = dom["bytes_per_launch"] / (dom_ms * 1e-3) / 1e9
+    rec.update({"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_ms": round(dom_ms, 5),
+                "traffic": traffic_for(dom["kernel"], blk.shape)})
+    if rec["traffic"] is not None:
+        rec["traffic_vs_algorithmic"] = round(rec["traffic"] / dom["bytes_per_launch"], 4)
+    # the passes' bytes against a plain copy's rate on the same GPU
+    return rec
+
+
+def cache_block_section(torch, fb, steps_timed: int) -> dict:
+    """The 256 x 256 x 128 complex128 block (uniform [-1,1) entries, seed 1,
+    20 steps).  Its 128 MiB grid fits the 256 MB last-level cache, so its
+    passes run above the HBM rate: reported as a cache-resident figure, warm
+    and with the cache flushed before each block."""
+    blk = SpectralBlock(torch, fb, CACHE_SHAPE, fb.FB_C128, CACHE_STEPS, seed=CACHE_SEED)
+    for _ in range(2):
+        blk.run()
+    t = time_replays(torch, blk.run, warmup=3, reps=steps_timed)
+    g = t.pop("graph")
+    flush = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cold = []
+    for _ in range(steps_timed):
+        flush.fill_(1)
+        s.record()
+        g.replay()
+        e.record()
+        torch.cuda.synchronize()
+        cold.append(s.elapsed_time(e))
+    del flush, g
+    ms = t["ms"]
+    rec = {"workload": "256x256x128 complex128 block (uniform [-1,1), seed 1): forward + 20 x (evolve + inverse "
+                       "+ checksum); the 128 MiB grid stays in the 256 MB last-level cache (not an HBM figure)",
+           "ms_per_block": round(ms, 4), "ms_median": round(t["ms_median"], 4),
+           "gflops": round(blk.flops() / (ms * 1e-3) / 1e9, 1),
+           "cache_flushed_ms_per_block": round(sorted(cold)[len(cold) // 2], 4)}
+    del blk
+    torch.cuda.empty_cache()
+    return rec
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -442,170 +634,81 @@ def main() -> int:
         print(json.dumps({"batched": batched_section(torch, fb)}), flush=True)
         return 0
 
-    plan = fb.Plan(*SHAPE, fb.FB_C128)
-    x0 = torch.empty(SHAPE, dtype=torch.complex128, device="cuda")
-    u0 = torch.empty_like(x0)
-    sums = torch.zeros((T_STEPS, 2), dtype=torch.float64, device="cuda")
-    fb.fb_fill_uniform(plan, x0, SEED)
-    xt = torch.empty_like(x0)
+    from paper_2004_09883_amd import inputs
 
-    def step():
-        fb.fb_fft3d_exec(plan, x0, u0, fb.FB_FORWARD)
-        for t in range(1, T_STEPS + 1):
-            fb.fb_spectral_step(plan, u0, xt, ALPHA, float(t), sums[t - 1])
-
+    host_x0 = inputs.gaussian_grid(SHAPE, SEED)
+    blk = SpectralBlock(torch, fb, SHAPE, fb.FB_C128, T_STEPS, host_x0=host_x0, schedule=HEADLINE_SCHEDULE)
     for _ in range(args.warmup):
-        step()
+        blk.run()
     torch.cuda.synchronize()
 
-    # per-kernel durations: the library brackets each of its launches with
-    # HIP events on the stream it launches on (eager launches)
+    # per-kernel records: the library brackets each of its launches with HIP
+    # events on the stream it launches on (eager launches, outside the timed
+    # region)
     fb.fb_profile_enable(True)
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        step()
-    stop.record()
+    for _ in range(2):
+        blk.run()
     torch.cuda.synchronize()
     prof = fb.fb_profile_report()
     fb.fb_profile_enable(False)
-    eager_ms = start.elapsed_time(stop) / args.steps
 
     # the timed region: the whole block captured once in a HIP graph and
-    # replayed, which removes the host launch gaps between its 83 kernels
-    graph = None
-    if not args.no_graph:
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            step()
-        for _ in range(args.warmup):
-            graph.replay()
-    run = graph.replay if graph is not None else step
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    start.record()
-    for _ in range(args.steps):
-        run()
-    stop.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
+    # replayed `steps` times back to back
+    t = time_replays(torch, blk.run, warmup=args.warmup, reps=args.steps, graph=not args.no_graph)
+    graph = t.pop("graph")
+    ms = t["ms"]
+    sums_headline = blk.sums.clone()
+    roofline = dominant_kernel_roofline(torch, fb, blk, prof)
+    launches = blk.launches()
+    del graph
 
-    ms = start.elapsed_time(stop) / args.steps
-
-    passes = [k for k in prof if k["kernel"].startswith("fft_pass")]
-    dom = max(passes, key=lambda k: k["total_ms"])
-    # The dominant kernel is the strided pass (the y and x axes), timed right
-    # after the timed region, before the extras below change the cache state.  Its
-    # average duration: 2 x 20 y and x passes back to back, launched from a
-    # HIP graph as the timed region is (replayed once before the timed
-    # replay), between two HIP events on the launch stream.  Also reported:
-    # the same in the context of the timed region, 20 x (z, y, x passes)
-    # minus 20 x (z pass), a difference of two timings and so noisier; and
-    # the per-launch events of the profiling hook above, which add their own
-    # record time to every launch.
-    reps = 20
-
-    def timed_graph(fn):
-        run_fn = fn
-        if graph is not None:
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g):
-                fn()
-            g.replay()
-            run_fn = g.replay
-        torch.cuda.synchronize()
-        start.record()
-        run_fn()
-        stop.record()
-        torch.cuda.synchronize()
-        return start.elapsed_time(stop)
-
-    def zyx():
-        for _ in range(reps):
-            for m in (1, 2, 4):
-                fb.fb_fft3d_exec_axes(plan, xt, xt, fb.FB_INVERSE, m)
-
-    def z_only():
-        for _ in range(reps):
-            fb.fb_fft3d_exec_axes(plan, xt, xt, fb.FB_INVERSE, 1)
-
-    def yx():
-        for _ in range(reps):
-            fb.fb_fft3d_exec_axes(plan, xt, xt, fb.FB_INVERSE, 2)
-            fb.fb_fft3d_exec_axes(plan, xt, xt, fb.FB_INVERSE, 4)
-
-    dom_ms = timed_graph(yx) / (2 * reps)
-    dom_ctx_ms = (timed_graph(zyx) - timed_graph(z_only)) / (2 * reps)
-    achieved = dom["bytes_per_launch"] / (dom_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom["kernel"]),
-                "kernel": dom["kernel"], "avg_launch_ms": round(dom_ms, 5),
-                "avg_launch_ms_after_z_pass": round(dom_ctx_ms, 5),
-                "avg_launch_ms_event_bracketed": round(dom["avg_ms"], 5),
-                "bytes_per_launch": dom["bytes_per_launch"]}
-
-    cold_ms = fused_ms = None
-    if not args.no_extras:
-        # the same block started cold: a 512 MiB write before each block
-        # evicts the grids from the 256 MB last-level cache (not timed)
-        flush = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")
-        cold = 0.0
-        for _ in range(args.steps):
-            flush.fill_(1)
-            start.record()
-            run()
-            stop.record()
-            torch.cuda.synchronize()
-            cold += start.elapsed_time(stop)
-        cold_ms = cold / args.steps
-        del flush
-
-    if not args.no_extras:
-        # the same block with the steps computed by fb_spectral_steps: chunks
-        # of up to 8 steps share their first inverse pass (one read of the
-        # spectrum), at the price of 20 output grids instead of one
-        xs = torch.empty((T_STEPS,) + SHAPE, dtype=torch.complex128, device="cuda")
-        sums_m = torch.zeros_like(sums)
-        ts = [float(t) for t in range(1, T_STEPS + 1)]
-
-        def step_fused():
-            fb.fb_fft3d_exec(plan, x0, u0, fb.FB_FORWARD)
-            fb.fb_spectral_steps(plan, u0, xs, ALPHA, ts, sums_m)
-
-        for _ in range(args.warmup):
-            step_fused()
-        torch.cuda.synchronize()
-        start.record()
-        for _ in range(args.steps):
-            step_fused()
-        stop.record()
-        torch.cuda.synchronize()
-        fused_ms = start.elapsed_time(stop) / args.steps
-        if not torch.equal(sums_m, sums):
-            print("fb_spectral_steps checksums differ from fb_spectral_step", file=sys.stderr)
-            return 1
-        del xs
-
-    flops_step = (1 + T_STEPS) * flops_fft(SHAPE)
-    value = flops_step / (ms * 1e-3) / 1e9
-    c = sums.cpu().numpy()
+    c = sums_headline.cpu().numpy()
     if not all(map(math.isfinite, c.reshape(-1))):
         print("non-finite checksum", file=sys.stderr)
         return 1
+
+    other = None
+    if not args.no_extras:
+        # the other schedule of the same block, for comparison; its checksums
+        # must equal the headline's bit for bit
+        sched = "fused_steps" if HEADLINE_SCHEDULE == "per_step" else "per_step"
+        del blk
+        torch.cuda.empty_cache()
+        blk2 = SpectralBlock(torch, fb, SHAPE, fb.FB_C128, T_STEPS, host_x0=host_x0, schedule=sched)
+        for _ in range(2):
+            blk2.run()
+        t2 = time_replays(torch, blk2.run, warmup=2, reps=max(3, args.steps // 2), graph=not args.no_graph)
+        t2.pop("graph")
+        if not torch.equal(blk2.sums, sums_headline):
+            print("the two schedules' checksums differ", file=sys.stderr)
+            return 1
+        other = {"schedule": sched, "ms_per_block": round(t2["ms"], 4), "launches": blk2.launches(),
+                 "gflops": round(blk2.flops() / (t2["ms"] * 1e-3) / 1e9, 1)}
+        blk = blk2
+    del blk
+    torch.cuda.empty_cache()
+
+    flops_step = (1 + T_STEPS) * flops_fft(SHAPE)
+    value = flops_step / (ms * 1e-3) / 1e9
+    n = math.prod(SHAPE)
+    b_block = (1 + T_STEPS) * 3 * 2 * 16 * n
     rec = {"metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic (SplitMix64 uniform [-1,1), seed 1)",
-           "config": {"workload": "spectral block 256x256x128 complex128: forward 3D FFT + 20 x (evolve "
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic (N(0,1) entries by Box-Muller, seed 2)",
+           "config": {"workload": "spectral block 512x256x256 complex128: forward 3D FFT + 10 x (evolve "
                                   "alpha=1e-6 + inverse 3D FFT + stride-17 checksum)",
                       "shape": list(SHAPE), "steps_per_block": T_STEPS, "alpha": ALPHA,
-                      "transforms_per_step": 1 + T_STEPS, "wall_s": round(wall, 3),
-                      "launch": "hip graph (one replay per step)" if graph is not None else "eager",
-                      "eager_ms_per_step": round(eager_ms, 4),
-                      "cache_flushed_ms_per_step": None if cold_ms is None else round(cold_ms, 4),
-                      "fused_steps_ms_per_step": None if fused_ms is None else round(fused_ms, 4)},
+                      "transforms_per_step": 1 + T_STEPS, "schedule": HEADLINE_SCHEDULE, "launches": launches,
+                      "wall_s": round(t["wall_s"], 3), "ms_median": round(t["ms_median"], 4),
+                      "ms_min": round(t["ms_min"], 4),
+                      "launch": "hip graph (one replay per step)" if not args.no_graph else "eager",
+                      "model_bytes_per_block": b_block,
+                      "block_hbm_roofline_frac": round(b_block / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                      "other_schedule": other},
            "roofline": roofline,
            "kernels": [{k: v for k, v in p.items()} for p in prof]}
+    if not args.no_extras:
+        rec["cache_block_256x256x128"] = cache_block_section(torch, fb, steps_timed=10)
     if not args.no_forms:
         rec["block_64x64x64"] = small_block_section(torch, fb)
         from paper_2004_09883_amd import offload
@@ -616,7 +719,7 @@ def main() -> int:
             rec["substitution_heat3d"] = substitute_run.heat3d_experiment()
         else:
             rec["substitution_heat3d"] = {"skipped": "gcc not available"}
-        rec["forms_512x256x256"] = forms_section(torch, fb)
+        rec["forms_512x256x256"] = forms_section(torch, fb, host_x0=host_x0, block_ms_c128=ms)
         rec["batched"] = batched_section(torch, fb)
         rec["paper_2d_2048"] = paper_2d_section(torch, fb)
         rec["lu_2048"] = lu_section(torch, fb)
@@ -633,7 +736,7 @@ def main() -> int:
                 sweep[str(int(rate))] = {k: r[k] for k in keys}
             rec["serving"]["rate_sweep"] = sweep
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline()
+        rec["cpu_baseline"] = cpu_baseline(host_x0=host_x0)
         if "paper_2d_2048" in rec:
             # the paper's unit: times faster than all-CPU processing, copies included
             import oracle

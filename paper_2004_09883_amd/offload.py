@@ -219,7 +219,8 @@ def search(torch, fb, shape=(64, 64, 64), alpha: float = 1e-6, steps: int = 6, s
         norm = max(1e-300, max(abs(v) for v in ref))
         err = max(abs(a - b) for a, b in zip(sums, ref)) / norm
         results.append({"pattern": "".join("G" if p[b] == "gpu" else "C" for b in BLOCKS), "seconds": secs,
-                        "transfers_per_step": transfers(p), "checksum_rel_err_vs_all_gpu": err})
+                        "transfers_per_step": transfers(p), "checksum_rel_err_vs_all_gpu": err,
+                        "checksums": [[v.real, v.imag] for v in sums]})
     best = min(results, key=lambda r: r["seconds"])
     cpu_only = next(r for r in results if r["pattern"] == "CCCC")
     greedy_name = "".join("G" if chosen[b] == "gpu" else "C" for b in BLOCKS)
@@ -236,6 +237,8 @@ def search(torch, fb, shape=(64, 64, 64), alpha: float = 1e-6, steps: int = 6, s
         "best_seconds": round(best["seconds"], 6),
         "all_cpu_seconds": round(cpu_only["seconds"], 6),
         "x_vs_all_cpu": round(cpu_only["seconds"] / best["seconds"], 1),
-        "patterns": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()} for r in results],
+        "patterns": [{k: (round(v, 6) if isinstance(v, float) and k != "checksum_rel_err_vs_all_gpu" else v)
+                      for k, v in r.items()} for r in results],
         "max_checksum_rel_err": max(r["checksum_rel_err_vs_all_gpu"] for r in results),
+        "all_gpu_checksums": [[v.real, v.imag] for v in ref],
     }

@@ -132,6 +132,42 @@ def test_fft3d_config3_full_size_c128():
     assert rel_l2(got, ref) < 1e-12
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_paper_2d_2048(dtype):
+    """The paper's own Fourier-transform size (section 5.1: a 2048 x 2048
+    grid), as the benchmark runs it (the 3D plan with nx = 1): forward and
+    inverse against the oracle on the same seeded input."""
+    shape = (1, 2048, 2048)
+    print(f"2048x2048 dtype={dtype}", flush=True)
+    for direction in (fb.FB_FORWARD, fb.FB_INVERSE):
+        got, ref = run_fft(shape, dtype, seed=7, direction=direction)
+        e = rel_l2(got, ref)
+        assert e < TOL[dtype], (direction, e)
+
+
+def test_headline_block_as_benchmarked():
+    """The benchmark's headline block at full size and in its launch
+    configuration (512 x 256 x 256 complex128, N(0,1) input seed 2, forward
+    + 10 fused steps, captured in a HIP graph and replayed): every step's
+    checksum and the last step's grid against the oracle."""
+    import bench
+    shape, steps = bench.SHAPE, bench.T_STEPS
+    x0 = inputs.gaussian_grid(shape, bench.SEED)
+    blk = bench.SpectralBlock(torch, fb, shape, fb.FB_C128, steps, host_x0=x0, schedule=bench.HEADLINE_SCHEDULE)
+    t = bench.time_replays(torch, blk.run, warmup=1, reps=2)
+    del t
+    sums = blk.sums.cpu().numpy()
+    last = host(blk.out if blk.schedule == "per_step" else blk.out[steps - 1])
+    del blk
+    torch.cuda.empty_cache()
+    X0 = oracle.fft3d(x0, -1)
+    for j in range(steps):
+        ref = oracle.fft3d(oracle.evolve(X0, bench.ALPHA, j + 1), +1)
+        assert checksum_err(complex(sums[j, 0], sums[j, 1]), ref) < 1e-12, j
+        if j == steps - 1:
+            assert rel_l2(last, ref) < 1e-12
+
+
 # ---------------------------------------------------------------- evolve / checksum / inputs
 
 @pytest.mark.parametrize("dtype", [fb.FB_C128, fb.FB_C64])
@@ -454,10 +490,22 @@ def test_offload_pattern_search():
     the host/device copies they need, and every one gives the all-device
     checksums (host blocks in numpy, device blocks through libfb)."""
     from paper_2004_09883_amd import offload
-    rep = offload.search(torch, fb, shape=(32, 32, 32), alpha=1e-3, steps=2)
+    shape, alpha, steps = (32, 32, 32), 1e-3, 2
+    rep = offload.search(torch, fb, shape=shape, alpha=alpha, steps=steps)
     print("offload search:", {k: rep[k] for k in ("greedy_pattern", "best_pattern", "x_vs_all_cpu")}, flush=True)
     assert len(rep["patterns"]) == 16
     assert rep["max_checksum_rel_err"] < 1e-12
+    # every pattern's checksums, the all-device one included, against the
+    # oracle's block on the same input (error normalised by sum_j |x[17 j]|)
+    want_sums, grids = oracle.spectral_block(inputs.uniform_grid(shape, 1), alpha, steps,
+                                             keep=set(range(1, steps + 1)))
+    for label, sums in [("GGGG", rep["all_gpu_checksums"])] + [(r["pattern"], r["checksums"])
+                                                                for r in rep["patterns"]]:
+        assert len(sums) == steps, label
+        for t in range(1, steps + 1):
+            got = complex(*sums[t - 1])
+            assert abs(got - want_sums[t - 1]) <= 1e-12 * abs(want_sums[t - 1]) or \
+                checksum_err(got, grids[t]) <= 1e-12, (label, t, got, want_sums[t - 1])
     assert rep["best_seconds"] <= rep["all_cpu_seconds"]
     assert set(rep["greedy_pattern"]) <= {"C", "G"} and len(rep["greedy_pattern"]) == 4
 
