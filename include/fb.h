@@ -121,16 +121,25 @@ fb_status fb_fft3d_exec_axes(const fb_plan *p, const void *in, void *out, int di
 /* Spectral evolution in place: u[k] *= exp(-(4 pi^2 alpha t) |k|^2), with
  * the signed wavenumber k = i - n [2i >= n] on each axis (heat-equation decay
  * of each Fourier mode on the unit periodic cube).  alpha >= 0, t >= 0,
- * both finite. */
+ * both finite.  The paper defines no evolution: this step, like the
+ * checksum below, belongs to the spectral-block workload built around the
+ * paper's Fourier-transform block (section 5.1(a)), a forward transform
+ * followed by per-step decay, inverse transform and checksum; it is
+ * offered as a library call of its own so that a detected block made of
+ * these steps can be replaced call by call (section 3.4, B-1). */
 fb_status fb_spectral_evolve(const fb_plan *p, void *u, double alpha, double t, void *hip_stream);
 
 /* Checksum: out2_dev[0] + i out2_dev[1] = sum_{j=0}^{1023} x.flat[(17 j) mod N],
  * accumulated in binary64 in a fixed order (deterministic).  out2_dev points
- * at two device doubles. */
+ * at two device doubles.  Not from the paper: the spectral-block workload's
+ * per-step check value (1024 samples at stride 17 of the normalised
+ * spatial grid). */
 fb_status fb_checksum(const fb_plan *p, const void *x, double *out2_dev, void *hip_stream);
 
-/* One step of the spectral block, fused: x_out = inverse(evolve(uhat0,
- * alpha, t)) and its checksum into out2_dev (when out2_dev is not NULL).
+/* One step of the spectral block, fused (the workload's step, see
+ * fb_spectral_evolve; the paper's block is replaced by one call of the same
+ * meaning, section 3.4 B-1): x_out = inverse(evolve(uhat0, alpha, t)) and
+ * its checksum into out2_dev (when out2_dev is not NULL).
  * uhat0 is read only and is not modified; x_out must not overlap uhat0.
  * The evolution is applied while the first inverse pass loads its input, so
  * it costs no extra pass over the grid. */

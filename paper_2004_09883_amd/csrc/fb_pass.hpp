@@ -66,13 +66,50 @@ template <typename V, int N, bool CONTIG> constexpr bool mx_capable()
 }
 
 // Streaming global access: the grid is read once and written once per pass,
-// so loads and stores can be marked non-temporal (FB_NT = 1).
-#ifndef FB_NT
-#define FB_NT 0
+// so loads and stores may be marked non-temporal (no allocation in the
+// caches).  Whether that pays depends on the pass; measured on MI355X at
+// 512x256x256 (per-pass durations, us):
+//  - complex128 contiguous passes, loads and stores: 204.7 -> 177.8;
+//  - complex128 strided passes, loads only: 208.9 -> 198.4 (n = 512) and
+//    178.6 -> 172.3 (n = 256); stores too: no further gain;
+//  - complex64 contiguous passes (vector and matrix-core): the whole block
+//    3.05 -> 2.96 ms and 3.69 -> 3.58 ms;
+//  - complex64 strided passes: loads 90.5 -> 103.7 (n = 512), all accesses
+//    up to 40 % slower: their 256 MiB grids partly stay in the 256 MB
+//    last-level cache between passes, which non-temporal accesses give up.
+// The choice is per pass kind, with build-time knobs.
+#ifndef FB_NT_C128_CONTIG
+#define FB_NT_C128_CONTIG 1
 #endif
-template <typename V> __device__ __forceinline__ V ld_stream(const V *p)
+#ifndef FB_NT_C128_STRIDED_LD
+#define FB_NT_C128_STRIDED_LD 1
+#endif
+#ifndef FB_NT_C128_STRIDED_ST
+#define FB_NT_C128_STRIDED_ST 0
+#endif
+#ifndef FB_NT_C64_CONTIG
+#define FB_NT_C64_CONTIG 1
+#endif
+#ifndef FB_NT_C64_STRIDED_LD
+#define FB_NT_C64_STRIDED_LD 0
+#endif
+#ifndef FB_NT_C64_STRIDED_ST
+#define FB_NT_C64_STRIDED_ST 0
+#endif
+template <typename V, bool CONTIG> constexpr bool nt_load()
 {
-    if constexpr (FB_NT) {
+    return std::is_same<V, double2>::value ? (CONTIG ? FB_NT_C128_CONTIG : FB_NT_C128_STRIDED_LD)
+                                           : (CONTIG ? FB_NT_C64_CONTIG : FB_NT_C64_STRIDED_LD);
+}
+template <typename V, bool CONTIG> constexpr bool nt_store()
+{
+    return std::is_same<V, double2>::value ? (CONTIG ? FB_NT_C128_CONTIG : FB_NT_C128_STRIDED_ST)
+                                           : (CONTIG ? FB_NT_C64_CONTIG : FB_NT_C64_STRIDED_ST);
+}
+
+template <bool NT, typename V> __device__ __forceinline__ V ld_stream(const V *p)
+{
+    if constexpr (NT) {
         typedef real_t<V> Rv __attribute__((ext_vector_type(2)));
         const Rv r = __builtin_nontemporal_load((const Rv *)p);
         return mk<V>(r.x, r.y);
@@ -80,9 +117,9 @@ template <typename V> __device__ __forceinline__ V ld_stream(const V *p)
         return *p;
     }
 }
-template <typename V> __device__ __forceinline__ void st_stream(V *p, V v)
+template <bool NT, typename V> __device__ __forceinline__ void st_stream(V *p, V v)
 {
-    if constexpr (FB_NT) {
+    if constexpr (NT) {
         typedef real_t<V> Rv __attribute__((ext_vector_type(2)));
         Rv r;
         r.x = v.x;
@@ -97,28 +134,28 @@ template <typename V> __device__ __forceinline__ void st_stream(V *p, V v)
 // complex64 elements read or written with one 16-byte access.
 template <typename V> using elem_t = typename std::conditional<std::is_same<V, c2x>::value, float2, V>::type;
 
-template <typename V> __device__ __forceinline__ V ld_v(const elem_t<V> *p)
+template <bool NT, typename V> __device__ __forceinline__ V ld_v(const elem_t<V> *p)
 {
     if constexpr (std::is_same<V, c2x>::value) {
         typedef float f4 __attribute__((ext_vector_type(4)));
         f4 r;
-        if constexpr (FB_NT) r = __builtin_nontemporal_load((const f4 *)p);
+        if constexpr (NT) r = __builtin_nontemporal_load((const f4 *)p);
         else r = *(const f4 *)p;
         return mk2(make_float2(r.x, r.y), make_float2(r.z, r.w));
     } else {
-        return ld_stream(p);
+        return ld_stream<NT>(p);
     }
 }
-template <typename V> __device__ __forceinline__ void st_v(elem_t<V> *p, V v)
+template <bool NT, typename V> __device__ __forceinline__ void st_v(elem_t<V> *p, V v)
 {
     if constexpr (std::is_same<V, c2x>::value) {
         typedef float f4 __attribute__((ext_vector_type(4)));
         f4 r;
         r.x = v.a.x; r.y = v.a.y; r.z = v.b.x; r.w = v.b.y;
-        if constexpr (FB_NT) __builtin_nontemporal_store(r, (f4 *)p);
+        if constexpr (NT) __builtin_nontemporal_store(r, (f4 *)p);
         else *(f4 *)p = r;
     } else {
-        st_stream(p, v);
+        st_stream<NT>(p, v);
     }
 }
 
@@ -225,7 +262,7 @@ struct MxGlobalIn {
         if (!h.ok) return make_float2(0.f, 0.f);
         float2 v = a->gen ? uniform_elem<float2>(a->gen_seed, (uint64_t)(h.p - (const float2 *)a->in) +
                                                                    (uint64_t)pos * (uint64_t)a->stride)
-                          : ld_stream(h.p + (int64_t)pos * a->stride);
+                          : ld_stream<false>(h.p + (int64_t)pos * a->stride);
         if (a->evolve) v = cscale(v, h.g * gtab[pos]);
         if (a->inv) v = cconj(v);
         return v;
@@ -262,7 +299,7 @@ struct MxGlobalOut {
         if (!h.ok) return;
         if (a->inv) v = cconj(v);
         if (a->scale != 1.0) v = cscale(v, (float)a->scale);
-        st_stream(h.p + (int64_t)pos * (a->ostride ? a->ostride : a->stride), v);
+        st_stream<false>(h.p + (int64_t)pos * (a->ostride ? a->ostride : a->stride), v);
     }
 };
 
@@ -317,9 +354,9 @@ __device__ __forceinline__ void store_tile_contiguous(const PassArgs &a, int64_t
             const int j = i / N, k = i - (i / N) * N;
             if constexpr (PAIR) {
                 const c2x &e = lds[(j >> 1) * LS + lds_pos(k)];
-                st_stream(o + i, (j & 1) ? e.b : e.a);
+                st_stream<nt_store<V, CONTIG>()>(o + i, (j & 1) ? e.b : e.a);
             } else {
-                st_stream(o + i, lds[j * LS + lds_pos(k)]);
+                st_stream<nt_store<V, CONTIG>()>(o + i, lds[j * LS + lds_pos(k)]);
             }
         }
     }
@@ -417,7 +454,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                         v[u * R0 + q] = uniform_elem<V>(a.gen_seed, (uint64_t)(base + (int64_t)(b + q * NBF0) * S));
                 } else {
 #pragma unroll
-                    for (int q = 0; q < R0; q++) v[u * R0 + q] = ld_v<V>(gin + (int64_t)(b + q * NBF0) * S);
+                    for (int q = 0; q < R0; q++) v[u * R0 + q] = ld_v<nt_load<V, CONTIG>(), V>(gin + (int64_t)(b + q * NBF0) * S);
                 }
             }
         }
@@ -717,12 +754,12 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                         if (a.scale != 1.0) o = cscale(o, sc);
                         if constexpr (PAIR) {
                             if (a.opair_step) {   // the pair's outputs are not adjacent
-                                st_stream(go + (int64_t)(b + q * NBF) * OS, o.a);
-                                st_stream(go + (int64_t)(b + q * NBF) * OS + a.opair_step, o.b);
+                                st_stream<nt_store<V, CONTIG>()>(go + (int64_t)(b + q * NBF) * OS, o.a);
+                                st_stream<nt_store<V, CONTIG>()>(go + (int64_t)(b + q * NBF) * OS + a.opair_step, o.b);
                                 continue;
                             }
                         }
-                        st_v<V>(go + (int64_t)(b + q * NBF) * OS, o);
+                        st_v<nt_store<V, CONTIG>(), V>(go + (int64_t)(b + q * NBF) * OS, o);
                     }
                 }
             }

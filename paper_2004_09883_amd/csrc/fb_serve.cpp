@@ -84,10 +84,14 @@ struct fb_server {
     size_t budget;
     int device;
     std::vector<Slot> slots;
+    // plans and pool belong to the worker thread (and to fb_server_destroy
+    // after the worker has joined); the figures fb_server_stats reports are
+    // atomics, so no other thread reads what the worker writes unguarded
     std::map<std::tuple<int64_t, int64_t, int64_t, int>, fb_plan *> plans;
     std::multimap<size_t, void *> pool;    // free device buffers by size
-    size_t bytes_allocated = 0;            // pooled + in use (device)
-    size_t peak_allocated = 0;
+    std::atomic<size_t> bytes_allocated{0};   // pooled + in use (device)
+    std::atomic<size_t> peak_allocated{0};
+    std::atomic<int> plans_cached{0};
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Pending> queue;
@@ -99,7 +103,7 @@ struct fb_server {
     std::atomic<int> policy{FB_SERVE_FIFO};
     int last_error = FB_OK;
     std::string last_msg;
-    int max_concurrent = 0;
+    std::atomic<int> max_concurrent{0};
 };
 
 namespace {
@@ -157,7 +161,7 @@ void *pool_get(fb_server *s, size_t bytes, hipError_t &e)
         return p;
     }
     // make room: give back pooled buffers of other sizes first
-    while (s->bytes_allocated + bytes > s->budget && !s->pool.empty()) {
+    while (s->bytes_allocated.load() + bytes > s->budget && !s->pool.empty()) {
         auto big = std::prev(s->pool.end());
         (void)hipFree(big->second);
         s->bytes_allocated -= big->first;
@@ -166,8 +170,8 @@ void *pool_get(fb_server *s, size_t bytes, hipError_t &e)
     void *p = nullptr;
     e = hipMalloc(&p, bytes);
     if (e != hipSuccess) return nullptr;
-    s->bytes_allocated += bytes;
-    if (s->bytes_allocated > s->peak_allocated) s->peak_allocated = s->bytes_allocated;
+    const size_t now = (s->bytes_allocated += bytes);
+    if (now > s->peak_allocated.load()) s->peak_allocated.store(now);   // only the worker writes it
     return p;
 }
 
@@ -180,7 +184,7 @@ void pool_put(fb_server *s, size_t bytes, void *p)
 // needs must fit in the budget (pooled free buffers can always be released).
 bool fits(fb_server *s, const fb_request &r)
 {
-    size_t in_use = s->bytes_allocated;
+    size_t in_use = s->bytes_allocated.load();
     for (auto &kv : s->pool) in_use -= kv.first;
     return in_use + request_bytes(r) <= s->budget;
 }
@@ -191,7 +195,10 @@ fb_plan *plan_for(fb_server *s, const fb_request &r)
     auto it = s->plans.find(key);
     if (it != s->plans.end()) return it->second;
     fb_plan *p = fb_fft3d_plan(r.nx, r.ny, r.nz, r.dtype);
-    if (p) s->plans[key] = p;
+    if (p) {
+        s->plans[key] = p;
+        s->plans_cached.store((int)s->plans.size());
+    }
     return p;
 }
 
@@ -310,7 +317,7 @@ void worker_loop(fb_server *s)
             sl.t_admit = now_s();
             int busy = 0;
             for (Slot &o : s->slots) busy += o.busy ? 1 : 0;
-            if (busy > s->max_concurrent) s->max_concurrent = busy;
+            if (busy > s->max_concurrent.load()) s->max_concurrent.store(busy);   // only the worker writes it
             const int rc = launch(s, sl);
             if (rc != FB_OK) {
                 (void)hipStreamSynchronize(sl.stream);
@@ -387,9 +394,15 @@ int64_t fb_server_submit(fb_server *s, const fb_request *r)
 int fb_server_poll(fb_server *s, fb_result *out, double *sums, int sums_cap, void *grid, size_t grid_cap)
 {
     if (!s || !out) return FB_ERR_INVALID_ARG;
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->done.empty()) return 0;
-    Done &d = s->done.front();
+    Done d;
+    {
+        // take the result out under the lock; copy it out after releasing
+        // the lock, so a large final grid does not hold up the worker
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->done.empty()) return 0;
+        d = std::move(s->done.front());
+        s->done.pop_front();
+    }
     *out = d.res;
     if (sums && sums_cap > 0) {
         const size_t n = d.sums.size() < (size_t)sums_cap ? d.sums.size() : (size_t)sums_cap;
@@ -397,7 +410,6 @@ int fb_server_poll(fb_server *s, fb_result *out, double *sums, int sums_cap, voi
     }
     out->grid_bytes = (int64_t)d.grid.size();
     if (grid && !d.grid.empty() && grid_cap >= d.grid.size()) memcpy(grid, d.grid.data(), d.grid.size());
-    s->done.pop_front();
     return 1;
 }
 
@@ -418,12 +430,12 @@ int fb_server_set_policy(fb_server *s, int policy)
 int fb_server_stats(fb_server *s, fb_server_info *info)
 {
     if (!s || !info) return FB_ERR_INVALID_ARG;
-    std::lock_guard<std::mutex> lk(s->mu);
     info->budget = s->budget;
-    info->bytes_allocated = s->bytes_allocated;
-    info->peak_allocated = s->peak_allocated;
-    info->plans_cached = (int)s->plans.size();
-    info->max_concurrent = s->max_concurrent;
+    info->bytes_allocated = s->bytes_allocated.load();
+    info->peak_allocated = s->peak_allocated.load();
+    info->plans_cached = s->plans_cached.load();
+    info->max_concurrent = s->max_concurrent.load();
+    std::lock_guard<std::mutex> lk(s->mu);
     info->queued = (int64_t)s->queue.size();
     return FB_OK;
 }

@@ -2,10 +2,14 @@
 against the continuous-batching request loop of libfb (fb_server_*) and
 reports throughput and end-to-end latency percentiles.
 
-Latency of a request = completion (checksums on the host) - arrival
-(submission), both stamped by the server on the host steady clock; it splits
-into queue wait (arrival -> admission) and service (admission -> completion).
-Requests arriving during the warm-up are served but not counted.
+Latency of a request = completion (checksums on the host, stamped by the
+server) - its scheduled arrival in the Poisson stream (start of the replay +
+the arrival offset), both on the host's monotonic clock; so a submit loop
+that falls behind the schedule shows up in the latency instead of hiding it
+(coordinated omission).  The part before the server's own arrival stamp is
+reported as submit lateness; the rest splits into queue wait (arrival stamp
+-> admission) and service (admission -> completion).  Requests arriving
+during the warm-up are served but not counted.
 """
 from __future__ import annotations
 
@@ -38,7 +42,11 @@ def request_flops(shape, steps: int) -> float:
 
 def run_serving(rate: float = 2000.0, duration: float = 10.0, warmup: float = 1.0, budget_bytes: float = 200e9,
                 n_streams: int = 8, seed_arrivals: int = 5, seed_payload: int = 4, alpha: float = 1e-6,
-                poll_every: int = 4, policy: int = fb.FB_SERVE_FIFO) -> dict:
+                poll_every: int = 4, policy: int = fb.FB_SERVE_FIFO, copy_gbs: float | None = None) -> dict:
+    """Replays the seeded stream once.  copy_gbs: a measured plain-copy
+    bandwidth of the same GPU; the offered load is then also reported
+    against it (rho against the practical ceiling as well as against the
+    8 TB/s peak)."""
     count = int(math.ceil((warmup + duration) * rate * 1.2)) + 16
     w = inputs.serving_workload(count, rate, seed_arrivals)
     keep = w["arrival"] < warmup + duration
@@ -55,11 +63,13 @@ def run_serving(rate: float = 2000.0, duration: float = 10.0, warmup: float = 1.
                 return
             results[r["id"]] = r
 
-    t0 = time.perf_counter()
+    # time.monotonic() and the server's std::chrono::steady_clock are both
+    # CLOCK_MONOTONIC on Linux, so scheduled arrivals and server stamps compare
+    t0 = time.monotonic()
     for j in range(n_req):
         target = t0 + arrival[j]
         while True:
-            now = time.perf_counter()
+            now = time.monotonic()
             if now >= target:
                 break
             if target - now > 5e-4:
@@ -80,10 +90,12 @@ def run_serving(rate: float = 2000.0, duration: float = 10.0, warmup: float = 1.
 
     measured = [rid for rid, m in meta.items() if m[4] >= warmup]
     bad = [rid for rid in meta if results[rid]["status"] != 0]
-    lat = np.array([results[r]["t_done"] - results[r]["t_arrival"] for r in measured])
+    sched = {r: t0 + meta[r][4] for r in measured}
+    late = np.array([results[r]["t_arrival"] - sched[r] for r in measured])
+    lat = np.array([results[r]["t_done"] - sched[r] for r in measured])
     wait = np.array([results[r]["t_admit"] - results[r]["t_arrival"] for r in measured])
     svc = np.array([results[r]["t_done"] - results[r]["t_admit"] for r in measured])
-    t_first = min(results[r]["t_arrival"] for r in measured)
+    t_first = min(sched[r] for r in measured)
     t_last = max(results[r]["t_done"] for r in measured)
     span = t_last - t_first
     model_bytes = sum(request_model_bytes(meta[r][1], meta[r][2], meta[r][3]) for r in measured)
@@ -100,12 +112,19 @@ def run_serving(rate: float = 2000.0, duration: float = 10.0, warmup: float = 1.
         "gflops": round(flops / span / 1e9, 1),
         "offered_load_rho": round(offered_bps / (HBM_PEAK_GBS * 1e9), 3),
         "offered_model_gbs": round(offered_bps / 1e9, 1),
+        "offered_load_rho_vs_copy": None if not copy_gbs else round(offered_bps / (copy_gbs * 1e9), 3),
+        "copy_gbs": copy_gbs,
         # served slower than requests arrived: the queue grows for the whole
         # run and the latency percentiles grow with its duration
         "saturated": bool(len(measured) / span < 0.97 * rate),
         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
         "mean_ms": round(float(lat.mean()) * 1e3, 3),
+        "latency_from": "scheduled arrival (start of replay + Poisson offset)",
+        "submit_lateness_p50_ms": round(float(np.percentile(late, 50)) * 1e3, 3),
+        "submit_lateness_p99_ms": round(float(np.percentile(late, 99)) * 1e3, 3),
+        "submit_lateness_max_ms": round(float(late.max()) * 1e3, 3),
+        "submit_lateness_min_ms": round(float(late.min()) * 1e3, 3),
         "queue_wait_p50_ms": round(float(np.percentile(wait, 50)) * 1e3, 3),
         "queue_wait_p99_ms": round(float(np.percentile(wait, 99)) * 1e3, 3),
         "service_p50_ms": round(float(np.percentile(svc, 50)) * 1e3, 3),
