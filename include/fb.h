@@ -111,6 +111,24 @@ fb_status fb_fft3d_exec(const fb_plan *p, const void *in, void *out, int dir, vo
  * fb_fft3d_exec.  Errors as fb_fft3d_exec, plus FB_ERR_OOM. */
 fb_status fb_fft3d_exec_host(const fb_plan *p, const void *in_host, void *out_host, int dir);
 
+/* Size of the static device staging buffer of fb_fft3d_exec_host_noalloc:
+ * 64 MiB, one 2048 x 2048 complex128 grid. */
+#define FB_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* fb_fft3d_exec_host without any device allocation, for callers that cannot
+ * allocate device memory (code that must not call hipMalloc: tight serving
+ * loops, harnesses that forbid allocation after start-up).  The grid is
+ * staged through a static device buffer of FB_STATIC_SCRATCH_BYTES that
+ * every GPU the library runs on holds until the process ends; the call
+ * itself allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine).  Grids larger than the buffer are rejected with
+ * FB_ERR_UNSUPPORTED_SIZE before any HIP call.  The buffer keeps the last
+ * call's grid; calls of one process on one GPU share it and are serialised
+ * by a process-wide lock (calls from other processes use their own copy).
+ * Synchronous; results equal fb_fft3d_exec_host's bit for bit.  Errors as
+ * fb_fft3d_exec_host, without FB_ERR_OOM. */
+fb_status fb_fft3d_exec_host_noalloc(const fb_plan *p, const void *in_host, void *out_host, int dir);
+
 /* The same transform restricted to some axes: bit 0 of `axes` selects z,
  * bit 1 y, bit 2 x (axes = 7 is fb_fft3d_exec).  The inverse divides by the
  * product of the selected lengths.  With no axis of length > 1 selected the

@@ -537,6 +537,37 @@ fb_status fb_fft3d_exec_host(const fb_plan *p, const void *in_host, void *out_ho
     return (fb_status)ok();
 }
 
+// Serialises the calls of fb_fft3d_exec_host_noalloc within the process:
+// they share one staging buffer per device.
+static std::mutex g_static_mu;
+
+fb_status fb_fft3d_exec_host_noalloc(const fb_plan *p, const void *in_host, void *out_host, int dir)
+{
+    if (check_plan(p)) return (fb_status)g_code;
+    if (!in_host || !out_host) return (fb_status)fail(FB_ERR_INVALID_ARG, "in_host / out_host is NULL");
+    if (dir != FB_FORWARD && dir != FB_INVERSE)
+        return (fb_status)fail(FB_ERR_INVALID_ARG, "dir must be FB_FORWARD (-1) or FB_INVERSE (+1), got %d", dir);
+    const size_t bytes = (size_t)p->N * (size_t)p->esize;
+    if (bytes > (size_t)FB_STATIC_SCRATCH_BYTES)
+        return (fb_status)fail(FB_ERR_UNSUPPORTED_SIZE,
+                               "grid of %zu bytes exceeds the %zu-byte static staging buffer of the "
+                               "allocation-free form (use fb_fft3d_exec_host)",
+                               bytes, (size_t)FB_STATIC_SCRATCH_BYTES);
+    if (check_device(p)) return (fb_status)g_code;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    void *d = nullptr;
+    hipError_t e = fb::static_scratch(&d);
+    if (e != hipSuccess) return (fb_status)hip_fail(e, "hipGetSymbolAddress (static staging buffer)");
+    e = hipMemcpy(d, in_host, bytes, hipMemcpyHostToDevice);
+    int rc = e != hipSuccess ? hip_fail(e, "host-to-device copy") : run_passes(p, d, d, dir, nullptr, nullptr);
+    if (!rc) {
+        e = hipMemcpy(out_host, d, bytes, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = hip_fail(e, "device-to-host copy");
+    }
+    if (rc) return (fb_status)rc;
+    return (fb_status)ok();
+}
+
 fb_status fb_fft3d_exec_axes(const fb_plan *p, const void *in, void *out, int dir, int axes, void *hip_stream)
 {
     if (check_plan(p) || check_grid_ptr(p, in, "in") || check_grid_ptr(p, out, "out")) return (fb_status)g_code;

@@ -108,6 +108,10 @@ hipError_t launch_evolve(int esize, const void *in, void *out, int64_t nx, int64
 // Checksums of `count` consecutive grids of N elements into out2[2g], out2[2g+1].
 hipError_t launch_checksum(int esize, const void *x, int64_t N, double *out2, hipStream_t st, int count = 1);
 
+// Device address of the current device's copy of the static staging buffer
+// (FB_STATIC_SCRATCH_BYTES), looked up once per device and cached.
+hipError_t static_scratch(void **ptr);
+
 // x[i] = U(seed, 2i) + i U(seed, 2i+1)  (SplitMix64, counter based)
 hipError_t launch_fill_uniform(int esize, void *x, int64_t N, uint64_t seed, hipStream_t st);
 

@@ -31,7 +31,7 @@ DTYPE_NAMES = {FB_C128: "c128", FB_C64: "c64", FB_C64_SPLITBF16: "c64_splitbf16"
 # every entry point declared in include/fb.h
 EXPORTS = ("fb_version", "fb_last_error", "fb_describe_shape", "fb_fft3d_plan", "fb_fft3d_destroy",
            "fb_plan_device_bytes", "fb_plan_describe", "fb_fft3d_exec", "fb_spectral_evolve",
-           "fb_checksum", "fb_spectral_step", "fb_spectral_steps", "fb_fft3d_exec_host", "fb_lu_factor", "fb_fill_uniform", "fb_fft3d_forward_uniform", "fb_fft3d_exec_axes",
+           "fb_checksum", "fb_spectral_step", "fb_spectral_steps", "fb_fft3d_exec_host", "fb_fft3d_exec_host_noalloc", "fb_lu_factor", "fb_fill_uniform", "fb_fft3d_forward_uniform", "fb_fft3d_exec_axes",
            "fb_profile_enable", "fb_profile_report", "fb_batch_plan", "fb_batch_destroy", "fb_batch_elements",
            "fb_batch_offsets", "fb_batch_workspace_bytes", "fb_batch_launches", "fb_batch_describe",
            "fb_batch_exec", "fb_server_create", "fb_server_submit", "fb_server_poll",
@@ -96,6 +96,7 @@ def load():
         "fb_spectral_step": (i32, [vp, vp, vp, dbl, dbl, vp, vp]),
         "fb_fill_uniform": (i32, [vp, vp, ctypes.c_uint64, vp]),
         "fb_fft3d_exec_host": (i32, [vp, vp, vp, i32]),
+        "fb_fft3d_exec_host_noalloc": (i32, [vp, vp, vp, i32]),
         "fb_lu_factor": (i32, [vp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp]),
         "fb_spectral_steps": (i32, [vp, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double), i32, vp, vp]),
         "fb_fft3d_forward_uniform": (i32, [vp, ctypes.c_uint64, vp, vp]),
@@ -324,6 +325,20 @@ def fb_fft3d_exec_host(plan: Plan, x_in, x_out, direction: int = FB_FORWARD):
         if a.shape != plan.shape or a.dtype != want or not a.flags["C_CONTIGUOUS"]:
             raise FbError(FB_ERR_INVALID_ARG, f"{name} must be a C-contiguous {want.__name__} array of shape {plan.shape}")
     _check(load().fb_fft3d_exec_host(plan.handle, x_in.ctypes.data, x_out.ctypes.data, direction))
+
+
+FB_STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def fb_fft3d_exec_host_noalloc(plan: Plan, x_in, x_out, direction: int = FB_FORWARD):
+    """As fb_fft3d_exec_host, staged through the library's static device
+    buffer (no device allocation; grids up to FB_STATIC_SCRATCH_BYTES)."""
+    import numpy as np
+    want = np.complex128 if plan.dtype == FB_C128 else np.complex64
+    for a, name in ((x_in, "x_in"), (x_out, "x_out")):
+        if a.shape != plan.shape or a.dtype != want or not a.flags["C_CONTIGUOUS"]:
+            raise FbError(FB_ERR_INVALID_ARG, f"{name} must be a C-contiguous {want.__name__} array of shape {plan.shape}")
+    _check(load().fb_fft3d_exec_host_noalloc(plan.handle, x_in.ctypes.data, x_out.ctypes.data, direction))
 
 
 def fb_spectral_steps(plan: Plan, uhat0, x_out, alpha: float, ts, sums=None, stream=None):

@@ -121,6 +121,7 @@ def test_lu_and_steps_reject_before_device():
     ts = (ctypes.c_double * 2)(1.0, 2.0)
     assert lib.fb_spectral_steps(None, 16, 16, 1e-6, ts, 2, None, None) == fb.FB_ERR_INVALID_ARG
     assert lib.fb_fft3d_exec_host(None, 16, 16, -1) == fb.FB_ERR_INVALID_ARG
+    assert lib.fb_fft3d_exec_host_noalloc(None, 16, 16, -1) == fb.FB_ERR_INVALID_ARG
     assert lib.fb_fft3d_forward_uniform(None, 1, 16, None) == fb.FB_ERR_INVALID_ARG
 
 
