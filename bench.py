@@ -130,12 +130,12 @@ def small_block_section(torch, fb, reps: int = 20) -> dict:
             "launches": 3 + steps * 4}
 
 
-def cpu_baseline(runs: int = 3, sample_steps: int = 3, host_x0=None) -> dict:
+def cpu_baseline(runs: int = 3, sample_steps: int = T_STEPS, host_x0=None) -> dict:
     """The oracle (plain C, binary64, OpenMP over pencils) on the host cores,
-    on a bounded sample of the headline workload: the forward 3D FFT of the
-    512 x 256 x 256 N(0,1) grid plus `sample_steps` of its 10
-    evolve/inverse/checksum steps, median of `runs`, scaled to GFLOP/s; and
-    one forward transform on one thread."""
+    on the headline workload: the forward 3D FFT of the 512 x 256 x 256
+    N(0,1) grid plus `sample_steps` of its 10 evolve/inverse/checksum steps
+    (all of them by default), median of `runs`, as GFLOP/s; and one forward
+    transform on one thread."""
     import oracle
     from paper_2004_09883_amd import inputs
 
@@ -283,8 +283,9 @@ def forms_section(torch, fb, reps: int = 50, steps: int = 10, host_x0=None, bloc
 
 def batched_section(torch, fb, reps: int = 10) -> dict:
     """4096 1D complex64 transforms of lengths drawn from {2^k, 3*2^k : 8 <= k
-    <= 16} (seed 3) plus 64 2D 512 x 512 ones, uniform inputs: one persistent
-    launch versus one launch per (length, pass) group."""
+    <= 16} (seed 3) plus 64 2D 512 x 512 ones, uniform inputs: the whole
+    batch in one persistent launch, versus one launch per (length, pass)
+    group and one persistent launch per phase."""
     from paper_2004_09883_amd import inputs
 
     lens = inputs.batch_lengths(4096, 3).tolist()
@@ -301,14 +302,20 @@ def batched_section(torch, fb, reps: int = 10) -> dict:
     for n in lens:
         model_bytes += (2 if n <= 4096 else 4) * 8 * n
     model_bytes += 64 * 4 * 8 * 512 * 512
-    # launches per execution: one per (length, pass) group, or one per phase
-    # of the persistent mode (the second phase only when a transform needs it)
+    # launches per execution: one per (length, pass) group; one for the whole
+    # batch; or one per phase of the per-phase persistent mode (the second
+    # phase only when a transform needs it)
     m = re.search(r"tiles=(\d+)\+(\d+)", batch.description)
     phases = 1 + (1 if m and int(m.group(2)) > 0 else 0)
+    one = "onelaunch=1" in batch.description
+    mb = re.search(r"balance=([0-9.]+)", batch.description)
     out = {"workload": "4096 1D complex64 FFTs, lengths uniform over {2^k, 3*2^k: 8<=k<=16} (seed 3), plus 64 "
                        "2D 512x512; uniform [-1,1) inputs", "transforms": 4096 + 64, "elements": batch.elements,
-           "model_bytes": model_bytes, "launches": {"per_group_launches": batch.launches, "persistent": phases}}
-    for mode, persistent in (("per_group_launches", False), ("persistent", True)):
+           "model_bytes": model_bytes, "plan": batch.description,
+           "single_launch_balance": float(mb.group(1)) if mb else None,
+           "launches": {"per_group_launches": batch.launches, "persistent": 1 if one else phases,
+                        "persistent_per_phase": phases}}
+    for mode, persistent in (("per_group_launches", 0), ("persistent", 1), ("persistent_per_phase", 2)):
         for _ in range(2):
             fb.fb_batch_exec(batch, x, y, wsp, fb.FB_FORWARD, persistent)
         torch.cuda.synchronize()
@@ -322,6 +329,7 @@ def batched_section(torch, fb, reps: int = 10) -> dict:
         out[mode] = {"ms": round(ms, 4), "gflops": round(flops / ms / 1e6, 1),
                      "hbm_roofline_frac": round(model_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
     out["persistent_speedup"] = round(out["per_group_launches"]["ms"] / out["persistent"]["ms"], 3)
+    out["persistent_per_phase_speedup"] = round(out["per_group_launches"]["ms"] / out["persistent_per_phase"]["ms"], 3)
     del x, y, ws, batch
     torch.cuda.empty_cache()
     return out

@@ -218,10 +218,17 @@ fb_status fb_lu_factor(double *a, int64_t n, int64_t lda, int32_t *ipiv, int32_t
  * lengths n = n1 n2 take two (a length-n1 pass over stride n2 into blocks of
  * n1, then a pre-twiddled length-n2 pass over stride n1); 2D transforms take
  * a row pass and a column pass.  The batch plan groups equal lengths so that
- * each (length, pass) group is one launch, or a persistent kernel runs the
- * tiles of all groups: one launch for the first phase (first passes, 2D
- * rows, single-pass lengths) and one for the second (second passes, 2D
- * columns), ordered on the stream. */
+ * each (length, pass) group is one launch; or one persistent kernel runs
+ * the whole batch in a single launch: each workgroup runs a list of items
+ * (both passes of a two-pass or 2D transform, one after the other, or one
+ * tile of a single-pass length) that the plan deals out largest first to
+ * the least-loaded workgroup; or a persistent kernel per phase runs the
+ * tiles of all groups of the phase (first passes, 2D rows and single-pass
+ * lengths, then second passes and 2D columns), ordered on the stream.  No
+ * form makes one workgroup wait for another.
+ * The buffers are one packed array of all transforms plus offsets (a reading
+ * of "pointer arrays": one allocation, one pointer per call; the offsets
+ * give each transform's start). */
 typedef struct fb_batch fb_batch;
 
 /* NULL on error.  dtype must be FB_C64.  Synchronous (builds tables). */
@@ -239,8 +246,11 @@ const char *fb_batch_describe(const fb_batch *b);
 /* Executes the batch: in and out are 16-byte aligned device buffers of
  * fb_batch_elements complex64 values (equal, or not overlapping).  workspace (256-byte
  * aligned, at least fb_batch_workspace_bytes(b, in == out) bytes) is needed
- * only in place; it may be NULL otherwise.  persistent = 1 uses the
- * persistent kernel (two launches), 0 one launch per group. */
+ * only in place; it may be NULL otherwise.  persistent = 0: one launch per
+ * group; 1: the whole batch in one launch (when every two-pass and 2D
+ * transform's tiles lie within that transform, which fb_batch_describe
+ * reports as onelaunch=1; otherwise as 2); 2: one persistent launch per
+ * phase.  All three give the same bits. */
 fb_status fb_batch_exec(const fb_batch *b, const void *in, void *out, void *workspace, size_t workspace_bytes,
                         int dir, int persistent, void *hip_stream);
 

@@ -286,6 +286,7 @@ int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, dou
     }
     args.inv = inv;
     args.scale = scale;
+    args.nt = (double)ngrids * (double)p->N * (double)p->esize >= (double)FB_NT_MIN_BYTES ? 1 : 0;
     if (ev) {
         args.evolve = 1;
         args.ev_c = ev->ev_c;
@@ -782,6 +783,14 @@ struct fb_batch {
     int device;
     int nblocks[2];                  // persistent grid per phase
     int lds_bytes[2];                // persistent LDS per phase: the largest tile kind of the phase
+    // the single-launch form: item lists per workgroup (empty when some
+    // transform's tiles straddle transforms, and the per-phase form is used)
+    bool onelaunch = false;
+    int ol_nblocks = 0, ol_lds_bytes = 0;
+    int64_t ol_items = 0;
+    double ol_balance = 0.0;         // largest workgroup load / mean load (model bytes)
+    fb::BatchItem *items_dev = nullptr;
+    int64_t *item_begin_dev = nullptr;
     std::string desc;
 };
 
@@ -834,6 +843,96 @@ void set_geom(PassArgs &a, int64_t npencils, int64_t segp, const int64_t *seg_of
     a.outer = outer;
     a.istep = istep;
     a.stride = stride;
+}
+
+int64_t gcd64(int64_t a, int64_t b) { return b == 0 ? a : gcd64(b, a % b); }
+
+// Smallest number of consecutive segments (transforms) of a group that its
+// tiles cover exactly: tiles hold tile_pencils pencils and start at pencil 0.
+int64_t segments_per_chunk(const fb::BatchGroup &g)
+{
+    const int64_t p = g.tile_pencils, sp = g.args.seg_pencils;
+    return p / gcd64(p, sp);
+}
+
+// Work items of the single-launch form and their order: the two passes of
+// every two-pass 1D transform and of every 2D transform as one item (of the
+// fewest consecutive transforms whose pencils both passes' tiles cover
+// exactly, usually one), every tile of a single-pass group as one item;
+// items are handed out by longest processing time first (largest model
+// bytes first, each to the workgroup with the least load so far), so that
+// the loads even out.  Returns false when a pair's chunks would not cover
+// its tiles (not expected: both passes see the same transforms).
+bool build_onelaunch_items(const std::vector<fb::BatchGroup> &groups, const std::vector<std::pair<int, int>> &pairs,
+                           const std::vector<int> &singles, int nwg, std::vector<fb::BatchItem> &items,
+                           std::vector<int64_t> &begin, double &balance)
+{
+    // model bytes of one tile: the transform data it reads and writes, plus
+    // a fixed allowance for the tile's latency (barriers, twiddles)
+    constexpr double kTileOverhead = 32768.0;
+    struct Cand {
+        fb::BatchItem it;
+        double cost;
+    };
+    std::vector<Cand> c;
+    for (const auto &pr : pairs) {
+        const fb::BatchGroup &g1 = groups[(size_t)pr.first], &g2 = groups[(size_t)pr.second];
+        const int64_t sp1 = g1.args.seg_pencils, sp2 = g2.args.seg_pencils;
+        if (g1.tile_pencils < 1 || g2.tile_pencils < 1 || sp1 < 1 || sp2 < 1) return false;
+        const int64_t nseg = g1.args.npencils / sp1;
+        if (nseg * sp1 != g1.args.npencils || nseg * sp2 != g2.args.npencils) return false;
+        const int64_t m1 = segments_per_chunk(g1), m2 = segments_per_chunk(g2);
+        const int64_t m = m1 / gcd64(m1, m2) * m2;   // transforms per item
+        const double seg_elems = (double)sp1 * (double)g1.n;   // = the transform's length
+        for (int64_t s0 = 0; s0 < nseg; s0 += m) {
+            const int64_t s1 = s0 + m < nseg ? s0 + m : nseg;
+            // tiles of g covering pencils [s0 sp, s1 sp): s0 sp is a tile boundary
+            auto range = [&](const fb::BatchGroup &g, int64_t sp, int64_t &a, int64_t &b) {
+                a = s0 * sp / g.tile_pencils;
+                b = s1 == nseg ? g.ntiles : s1 * sp / g.tile_pencils;
+            };
+            fb::BatchItem it{pr.first, pr.second, 0, 0, 0, 0};
+            range(g1, sp1, it.a1, it.b1);
+            range(g2, sp2, it.a2, it.b2);
+            const double cost = 2.0 * 16.0 * seg_elems * (double)(s1 - s0) +
+                                kTileOverhead * (double)(it.b1 - it.a1 + it.b2 - it.a2);
+            c.push_back({it, cost});
+        }
+    }
+    for (int gi : singles) {
+        const fb::BatchGroup &g = groups[(size_t)gi];
+        const double per_tile = (double)g.args.npencils * (double)g.n * 16.0 / (double)g.ntiles + kTileOverhead;
+        for (int64_t t = 0; t < g.ntiles; t++) c.push_back({{gi, -1, t, t + 1, 0, 0}, per_tile});
+    }
+    std::stable_sort(c.begin(), c.end(), [](const Cand &x, const Cand &y) { return x.cost > y.cost; });
+    // least-loaded workgroup first (ties: lower index), by a binary heap
+    std::vector<std::pair<double, int>> heap;
+    for (int w = 0; w < nwg; w++) heap.push_back({0.0, w});
+    auto gt = [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
+        return x.first > y.first || (x.first == y.first && x.second > y.second);
+    };
+    std::make_heap(heap.begin(), heap.end(), gt);
+    std::vector<std::vector<fb::BatchItem>> per(nwg);
+    std::vector<double> load(nwg, 0.0);
+    for (const Cand &x : c) {
+        std::pop_heap(heap.begin(), heap.end(), gt);
+        auto &top = heap.back();
+        per[(size_t)top.second].push_back(x.it);
+        top.first += x.cost;
+        load[(size_t)top.second] = top.first;
+        std::push_heap(heap.begin(), heap.end(), gt);
+    }
+    items.clear();
+    begin.assign(1, 0);
+    double mx = 0.0, sum = 0.0;
+    for (int w = 0; w < nwg; w++) {
+        for (const auto &it : per[(size_t)w]) items.push_back(it);
+        begin.push_back((int64_t)items.size());
+        mx = load[(size_t)w] > mx ? load[(size_t)w] : mx;
+        sum += load[(size_t)w];
+    }
+    balance = sum > 0.0 ? mx / (sum / nwg) : 1.0;
+    return true;
 }
 
 // Largest element touched by a group, relative to its segment start.
@@ -965,8 +1064,8 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
             g.out_sel = 1;
             g.last = 1;
             g.inv_scale = 1.0 / (double)L;
-            g.ntiles = (cnt + fb::find_pass(esize, (int)L, true, false).pencils_per_wg - 1) /
-                       fb::find_pass(esize, (int)L, true, false).pencils_per_wg;
+            g.tile_pencils = fb::find_pass(esize, (int)L, true, false).pencils_per_wg;
+            g.ntiles = (cnt + g.tile_pencils - 1) / g.tile_pencils;
             if (!group_in_bounds(g, segmax, b->total)) e = hipErrorInvalidValue;
             single.push_back(g);
         } else {
@@ -989,6 +1088,7 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
             // block of P1 n1 elements: write it whole when tiles do not straddle
             // transforms
             g1.args.otile = (n2 % P1 == 0) ? 1 : 0;
+            g1.tile_pencils = P1;
             // pass 2: pre-twiddle w_L^(q b), length-n2 DFTs over b < n1 (elements b + q n1)
             fb::BatchGroup g2 = new_group(n2, false);
             set_geom(g2.args, cnt * n1, n1, soff, n1, 0, 1, n1);
@@ -1008,6 +1108,7 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
             g2.inv_scale = 1.0 / (double)L;
             const int P2 = fb::find_pass_pair((int)n2).pencils_per_wg;
             g2.ntiles = (cnt * n1 + P2 - 1) / P2;
+            g2.tile_pencils = P2;
             // the pass-2 kernel reads the pre-twiddle table at the element's offset
             // within its transform (< n2 n1)
             if (!group_in_bounds(g1, segmax, b->total) || !group_in_bounds(g2, segmax, b->total) ||
@@ -1032,6 +1133,7 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
         rows.out_sel = 1;
         rows.ntiles = (n2d * s + fb::find_pass(esize, (int)s, true, false).pencils_per_wg - 1) /
                       fb::find_pass(esize, (int)s, true, false).pencils_per_wg;
+        rows.tile_pencils = fb::find_pass(esize, (int)s, true, false).pencils_per_wg;
         cols = new_group(s, false);
         set_geom(cols.args, n2d * s, s, soff, s, 0, 1, s);
         cols.in_sel = 1;
@@ -1041,6 +1143,7 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
         cols.inv_scale = 1.0 / (double)(s * s);
         cols.ntiles = (n2d * s + fb::find_pass_pair((int)s).pencils_per_wg - 1) /
                       fb::find_pass_pair((int)s).pencils_per_wg;
+        cols.tile_pencils = fb::find_pass_pair((int)s).pencils_per_wg;
         if (e == hipSuccess && (!group_in_bounds(rows, o2.back(), b->total) || !group_in_bounds(cols, o2.back(), b->total)))
             e = hipErrorInvalidValue;
     }
@@ -1096,11 +1199,50 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
         return nullptr;
     }
     for (int ph = 0; ph < 2; ph++) b->nblocks[ph] = (per_cu[ph] > 0 ? per_cu[ph] : 1) * (cus > 0 ? cus : 1);
-    char d[256];
+
+    // the single-launch form: one grid sized for the largest tile kind of
+    // either phase; item lists per workgroup
+    {
+        const int np1 = (int)pass1.size();
+        std::vector<std::pair<int, int>> pairs;
+        for (int i = 0; i < np1; i++) pairs.push_back({i, b->phase1_begin + i});
+        if (has2d) pairs.push_back({np1, b->phase1_begin + (int)pass2.size()});
+        std::vector<int> singles;
+        for (int i = np1 + (has2d ? 1 : 0); i < b->phase1_begin; i++) singles.push_back(i);
+        b->ol_lds_bytes = b->lds_bytes[0] > b->lds_bytes[1] ? b->lds_bytes[0] : b->lds_bytes[1];
+        int per = 0;
+        e = fb::batch_occupancy(b->ol_lds_bytes, &per, true);
+        if (e == hipSuccess) {
+            b->ol_nblocks = (per > 0 ? per : 1) * (cus > 0 ? cus : 1);
+            std::vector<fb::BatchItem> items;
+            std::vector<int64_t> begin;
+            if (build_onelaunch_items(b->groups, pairs, singles, b->ol_nblocks, items, begin, b->ol_balance)) {
+                b->items_dev = dev_alloc<fb::BatchItem>(b, items.size() ? items.size() : 1, e);
+                if (e == hipSuccess) b->item_begin_dev = dev_alloc<int64_t>(b, begin.size(), e);
+                if (e == hipSuccess && !items.empty())
+                    e = hipMemcpy(b->items_dev, items.data(), items.size() * sizeof(fb::BatchItem),
+                                  hipMemcpyHostToDevice);
+                if (e == hipSuccess)
+                    e = hipMemcpy(b->item_begin_dev, begin.data(), begin.size() * sizeof(int64_t),
+                                  hipMemcpyHostToDevice);
+                b->onelaunch = e == hipSuccess;
+                b->ol_items = (int64_t)items.size();
+            }
+        }
+        if (e != hipSuccess) {
+            hip_fail(e, "batch plan (single-launch items)");
+            batch_free(b);
+            delete b;
+            return nullptr;
+        }
+    }
+    char d[384];
     snprintf(d, sizeof d,
-             "batch n1d=%d n2d=%d side=%lld groups=%d tiles=%lld+%lld elements=%lld persistent grid=%d+%d lds=%d+%d",
+             "batch n1d=%d n2d=%d side=%lld groups=%d tiles=%lld+%lld elements=%lld persistent grid=%d+%d lds=%d+%d "
+             "onelaunch=%d items=%lld grid=%d lds=%d balance=%.3f",
              n1d, n2d, (long long)side2d, (int)b->groups.size(), (long long)b->ntasks[0], (long long)b->ntasks[1],
-             (long long)b->total, b->nblocks[0], b->nblocks[1], b->lds_bytes[0], b->lds_bytes[1]);
+             (long long)b->total, b->nblocks[0], b->nblocks[1], b->lds_bytes[0], b->lds_bytes[1],
+             b->onelaunch ? 1 : 0, (long long)b->ol_items, b->ol_nblocks, b->ol_lds_bytes, b->ol_balance);
     b->desc = d;
     ok();
     return b;
@@ -1141,6 +1283,8 @@ fb_status fb_batch_exec(const fb_batch *b, const void *in, void *out, void *work
         return (fb_status)fail(FB_ERR_INVALID_ARG, "in/out must be non-NULL and 16-byte aligned");
     if (dir != FB_FORWARD && dir != FB_INVERSE)
         return (fb_status)fail(FB_ERR_INVALID_ARG, "dir must be FB_FORWARD (-1) or FB_INVERSE (+1), got %d", dir);
+    if (persistent < 0 || persistent > 2)
+        return (fb_status)fail(FB_ERR_INVALID_ARG, "persistent must be 0, 1 or 2, got %d", persistent);
     const size_t bytes = (size_t)b->total * 8;
     const uintptr_t x = (uintptr_t)in, y = (uintptr_t)out;
     const bool in_place = x == y;
@@ -1168,6 +1312,15 @@ fb_status fb_batch_exec(const fb_batch *b, const void *in, void *out, void *work
     bufs.p[1] = out;
     bufs.p[2] = mid;
     bufs.inv = dir > 0;
+    bufs.nt = (double)b->total * 8.0 >= (double)FB_NT_MIN_BYTES ? 1 : 0;
+    if (persistent == 1 && b->onelaunch) {
+        e = timed_launch("batch_onelaunch<c64>", 0.0, st, [&] {
+            return fb::launch_batch_onelaunch(b->groups_dev, b->items_dev, b->item_begin_dev, b->ol_nblocks,
+                                              b->ol_lds_bytes, bufs, st);
+        });
+        if (e != hipSuccess) return (fb_status)hip_fail(e, "single-launch batch");
+        return (fb_status)ok();
+    }
     if (persistent) {
         const int ng = (int)b->groups.size();
         e = timed_launch("batch_persistent<c64,phase0>", 0.0, st, [&] {
@@ -1187,6 +1340,7 @@ fb_status fb_batch_exec(const fb_batch *b, const void *in, void *out, void *work
         a.in = bufs.p[g.in_sel];
         a.out = bufs.p[g.out_sel];
         a.inv = bufs.inv;
+        a.nt = bufs.nt;
         a.scale = (bufs.inv && g.last) ? g.inv_scale : 1.0;
         // contiguous groups move complex64 pencils, strided groups pencil pairs
         const PassInfo pi = g.contig ? fb::find_pass(8, g.n, true, false) : fb::find_pass_pair(g.n);

@@ -1,13 +1,18 @@
 // fb_batch.hip -- device side of the batched form: many independent 1D and
-// 2D complex64 transforms of mixed lengths, executed either as one launch
-// per (length, pass) group or as a single persistent launch that takes the
-// tiles of every group from a work queue.
+// 2D complex64 transforms of mixed lengths, executed as one launch per
+// (length, pass) group, as one persistent launch per phase, or as a single
+// persistent launch for the whole batch.
 //
 // A batch is a list of groups; every group is one pencil pass (PassArgs)
 // over all transforms of one length, with `ntiles` tiles.  Groups come in
 // two phases: phase 0 holds the first passes of two-pass long transforms,
 // the row passes of 2D transforms and the single-pass lengths; phase 1 the
 // second passes and the column passes, which read what phase 0 wrote.
+//
+// None of the persistent forms communicates between workgroups: the
+// per-phase form orders its phases on the stream, and the single launch
+// gives each two-pass transform (both passes) to one workgroup, which runs
+// the second pass after its own first pass and a barrier.
 #include <hip/hip_runtime.h>
 
 #include "fb_batch.hpp"
@@ -87,6 +92,7 @@ __device__ __forceinline__ void tile_fn(const BatchGroup *g, const BatchBuffers 
     a.in = bufs.p[g->in_sel];
     a.out = bufs.p[g->out_sel];
     a.inv = bufs.inv;
+    a.nt = bufs.nt;
     a.scale = (bufs.inv && g->last) ? g->inv_scale : 1.0;
     if constexpr (CONTIG) pass_tile<float2, L, true, false>(a, tile, tid, (float2 *)lds, nullptr);
     else pass_tile<c2x, L, false, false>(a, tile, tid, lds, nullptr);
@@ -135,8 +141,53 @@ hipError_t launch_batch_persistent(const BatchGroup *groups_dev, int g0, int g1,
     return hipGetLastError();
 }
 
-hipError_t batch_occupancy(int lds_bytes, int *blocks_per_cu)
+// The whole batch in one launch.  Workgroup w runs its items in order; an
+// item is a range of tiles of one group, or the two passes of one transform
+// (or one 2D transform): the first pass's tiles, then the second pass's,
+// which read what the first wrote.  Both ranges run in this workgroup, so
+// the barrier after each tile (a workgroup-scope release and acquire) is
+// all the ordering they need.  The host builds the item lists (largest item
+// first onto the least-loaded workgroup), so no workgroup waits for
+// another.
+__global__ void __launch_bounds__(BATCH_THREADS) batch_onelaunch(const BatchGroup *__restrict__ groups,
+                                                                 const BatchItem *__restrict__ items,
+                                                                 const int64_t *__restrict__ item_begin,
+                                                                 BatchBuffers bufs)
 {
+    extern __shared__ c2x lds[];
+    const int tid = threadIdx.x;
+    const int64_t i0 = item_begin[blockIdx.x], i1 = item_begin[blockIdx.x + 1];
+    for (int64_t it = i0; it < i1; it++) {
+        const BatchItem item = items[it];
+        for (int64_t t = item.a1; t < item.b1; t++) {
+            run_tile(groups + item.g1, bufs, t, tid, lds);
+            __syncthreads();   // the next tile reuses the LDS; the second range reads this one's output
+        }
+        if (item.g2 >= 0) {
+            for (int64_t t = item.a2; t < item.b2; t++) {
+                run_tile(groups + item.g2, bufs, t, tid, lds);
+                __syncthreads();
+            }
+        }
+    }
+}
+
+hipError_t launch_batch_onelaunch(const BatchGroup *groups_dev, const BatchItem *items_dev,
+                                  const int64_t *item_begin_dev, int nblocks, int lds_bytes, const BatchBuffers &bufs,
+                                  hipStream_t st)
+{
+    if (nblocks <= 0) return hipSuccess;
+    if (lds_bytes <= 0 || lds_bytes > BATCH_LDS_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(batch_onelaunch, dim3((unsigned)nblocks), dim3(BATCH_THREADS), (unsigned)lds_bytes, st,
+                       groups_dev, items_dev, item_begin_dev, bufs);
+    return hipGetLastError();
+}
+
+hipError_t batch_occupancy(int lds_bytes, int *blocks_per_cu, bool onelaunch)
+{
+    if (onelaunch)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_onelaunch, BATCH_THREADS,
+                                                            (size_t)lds_bytes);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent, BATCH_THREADS,
                                                         (size_t)lds_bytes);
 }

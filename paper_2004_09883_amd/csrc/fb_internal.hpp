@@ -44,6 +44,9 @@ struct PassArgs {
     // instead of a load from `in`
     int gen;
     uint64_t gen_seed;
+    // non-temporal global accesses allowed (for the pass kinds that gain from
+    // them): set when the data the pass sweeps exceeds the last-level cache
+    int nt;
     int inv;            // 1: inverse (conjugate on load and on store)
     double scale;       // applied on store (1/N in the last inverse pass)
     // fused spectral evolution (contiguous passes only): element i of pencil
@@ -60,6 +63,13 @@ struct PassArgs {
     int64_t out_step;
     double ev_cs[FB_MAX_FUSED_STEPS];
 };
+
+// Data swept by one pass above which its global accesses may be
+// non-temporal (the MI355X last-level cache is 256 MB; grids of 128 MiB and
+// less gain from it between passes).
+#ifndef FB_NT_MIN_BYTES
+#define FB_NT_MIN_BYTES (192ll << 20)
+#endif
 
 using PassLauncher = hipError_t (*)(const PassArgs &, hipStream_t);
 

@@ -77,7 +77,12 @@ template <typename V, int N, bool CONTIG> constexpr bool mx_capable()
 //  - complex64 strided passes: loads 90.5 -> 103.7 (n = 512), all accesses
 //    up to 40 % slower: their 256 MiB grids partly stay in the 256 MB
 //    last-level cache between passes, which non-temporal accesses give up.
-// The choice is per pass kind, with build-time knobs.
+// The choice is per pass kind, with build-time knobs, and per launch: the
+// host sets PassArgs::nt only when the data a pass sweeps is larger than
+// the last-level cache (FB_NT_MIN_BYTES), since a grid that fits it (the
+// 128 MiB 256x256x128 complex128 block, the 64 MiB 2048x2048 one) gains
+// from the cache between passes: that block took 2.96 ms per 20 steps with
+// non-temporal accesses against 2.69 ms without.
 #ifndef FB_NT_C128_CONTIG
 #define FB_NT_C128_CONTIG 1
 #endif
@@ -350,15 +355,20 @@ __device__ __forceinline__ void store_tile_contiguous(const PassArgs &a, int64_t
         const int64_t np = a.npencils - p0 < P * UNIT ? a.npencils - p0 : P * UNIT;
         const int count = (int)np * N;
         elem_t<V> *o = (elem_t<V> *)a.out + ob;
-        for (int i = tid; i < count; i += Cfg::THREADS) {
-            const int j = i / N, k = i - (i / N) * N;
-            if constexpr (PAIR) {
-                const c2x &e = lds[(j >> 1) * LS + lds_pos(k)];
-                st_stream<nt_store<V, CONTIG>()>(o + i, (j & 1) ? e.b : e.a);
-            } else {
-                st_stream<nt_store<V, CONTIG>()>(o + i, lds[j * LS + lds_pos(k)]);
+        auto store_all = [&](auto ntc) {
+            constexpr bool NT = decltype(ntc)::value;
+            for (int i = tid; i < count; i += Cfg::THREADS) {
+                const int j = i / N, k = i - (i / N) * N;
+                if constexpr (PAIR) {
+                    const c2x &e = lds[(j >> 1) * LS + lds_pos(k)];
+                    st_stream<NT>(o + i, (j & 1) ? e.b : e.a);
+                } else {
+                    st_stream<NT>(o + i, lds[j * LS + lds_pos(k)]);
+                }
             }
-        }
+        };
+        if (nt_store<V, CONTIG>() && a.nt) store_all(std::true_type{});
+        else store_all(std::false_type{});
     }
 }
 
@@ -443,20 +453,34 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
     }
 
     // ---- stage 0 input: global loads (or generated values), pattern b + q N/R0
-    if (valid && !MX_IN) {
+    // global loads, non-temporal when this pass kind gains from it and the
+    // grid is larger than the last-level cache (PassArgs::nt)
+    auto load_all = [&](auto ntc) {
+        constexpr bool NT = decltype(ntc)::value;
 #pragma unroll
         for (int u = 0; u < U0; u++) {
             const int b = t + T * u;
             if (NBF0 % T == 0 || b < NBF0) {
-                if (a.gen) {
+#pragma unroll
+                for (int q = 0; q < R0; q++) v[u * R0 + q] = ld_v<NT, V>(gin + (int64_t)(b + q * NBF0) * S);
+            }
+        }
+    };
+    if (valid && !MX_IN) {
+        if (a.gen) {
+#pragma unroll
+            for (int u = 0; u < U0; u++) {
+                const int b = t + T * u;
+                if (NBF0 % T == 0 || b < NBF0) {
 #pragma unroll
                     for (int q = 0; q < R0; q++)
                         v[u * R0 + q] = uniform_elem<V>(a.gen_seed, (uint64_t)(base + (int64_t)(b + q * NBF0) * S));
-                } else {
-#pragma unroll
-                    for (int q = 0; q < R0; q++) v[u * R0 + q] = ld_v<nt_load<V, CONTIG>(), V>(gin + (int64_t)(b + q * NBF0) * S);
                 }
             }
+        } else if (nt_load<V, CONTIG>() && a.nt) {
+            load_all(std::true_type{});
+        } else {
+            load_all(std::false_type{});
         }
     }
     if constexpr (MULTI) {
@@ -740,7 +764,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                 return;
             }
         }
-        if (valid && !MX_OUT) {
+        auto store_all = [&](auto ntc) {
+            constexpr bool NT = decltype(ntc)::value;
             const R sc = (R)a.scale;
             E *__restrict__ go = MULTI ? gout + rep * a.out_step : gout;
 #pragma unroll
@@ -754,15 +779,19 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                         if (a.scale != 1.0) o = cscale(o, sc);
                         if constexpr (PAIR) {
                             if (a.opair_step) {   // the pair's outputs are not adjacent
-                                st_stream<nt_store<V, CONTIG>()>(go + (int64_t)(b + q * NBF) * OS, o.a);
-                                st_stream<nt_store<V, CONTIG>()>(go + (int64_t)(b + q * NBF) * OS + a.opair_step, o.b);
+                                st_stream<NT>(go + (int64_t)(b + q * NBF) * OS, o.a);
+                                st_stream<NT>(go + (int64_t)(b + q * NBF) * OS + a.opair_step, o.b);
                                 continue;
                             }
                         }
-                        st_v<nt_store<V, CONTIG>(), V>(go + (int64_t)(b + q * NBF) * OS, o);
+                        st_v<NT, V>(go + (int64_t)(b + q * NBF) * OS, o);
                     }
                 }
             }
+        };
+        if (valid && !MX_OUT) {
+            if (nt_store<V, CONTIG>() && a.nt) store_all(std::true_type{});
+            else store_all(std::false_type{});
         }
     }
     };   // outputs

@@ -411,16 +411,18 @@ def fb_batch_plan(lens, n2d: int = 0, side2d: int = 0, dtype: int = FB_C64) -> B
     return Batch(lens, n2d, side2d, dtype)
 
 
-def fb_batch_exec(batch: Batch, x_in, x_out, workspace, direction: int = FB_FORWARD, persistent: bool = True,
+def fb_batch_exec(batch: Batch, x_in, x_out, workspace, direction: int = FB_FORWARD, persistent=True,
                   stream=None):
     """x_in/x_out: complex64 device tensors of batch.elements values; workspace:
-    a device tensor (uint8) of at least batch.workspace_bytes(x_in is x_out)."""
+    a device tensor (uint8) of at least batch.workspace_bytes(x_in is x_out).
+    persistent: False/0 one launch per group, True/1 the whole batch in one
+    launch, 2 one persistent launch per phase."""
     for t, name in ((x_in, "in"), (x_out, "out")):
         if not isinstance(t, int) and (t.numel() != batch.elements or not t.is_contiguous()):
             raise FbError(FB_ERR_INVALID_ARG, f"{name} must be a contiguous tensor of {batch.elements} elements")
     wbytes = workspace.numel() * workspace.element_size() if not isinstance(workspace, int) else 1 << 62
     _check(load().fb_batch_exec(batch.handle, _ptr(x_in), _ptr(x_out), _ptr(workspace), wbytes, direction,
-                                1 if persistent else 0, _stream(stream)))
+                                int(persistent), _stream(stream)))
 
 
 

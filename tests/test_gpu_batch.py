@@ -1,7 +1,9 @@
 """GPU parity of the batched form: many independent complex64 1D transforms
 of mixed lengths plus 2D transforms, as one launch per (length, pass) group
-or as one persistent launch, against the oracle transform by transform
-(rel L2 <= 1e-5 each, on the complex64-rounded inputs)."""
+(mode 0), as a single persistent launch for the whole batch (mode 1) or as
+one persistent launch per phase (mode 2), against the oracle transform by
+transform (rel L2 <= 1e-5 each, on the complex64-rounded inputs); the three
+modes run the same tile code and must agree bit for bit."""
 import numpy as np
 import pytest
 
@@ -48,7 +50,10 @@ MIXED = [256, 768, 4096, 3072, 6144, 8192, 24576, 65536, 196608, 12, 2, 3, 48, 5
          32768, 49152, 1536, 2048]
 
 
-@pytest.mark.parametrize("persistent", [False, True])
+MODES = (0, 1, 2)
+
+
+@pytest.mark.parametrize("persistent", MODES)
 @pytest.mark.parametrize("in_place", [False, True])
 @pytest.mark.parametrize("direction", [fb.FB_FORWARD, fb.FB_INVERSE])
 def test_mixed_batch(persistent, in_place, direction):
@@ -65,12 +70,17 @@ def test_mixed_batch(persistent, in_place, direction):
 
 def test_persistent_equals_per_group_bitwise():
     batch = fb.Batch(MIXED, n2d=2, side2d=512)
+    assert "onelaunch=1" in batch.description, batch.description
     x = packed_input(batch, 5)
-    a = run(batch, x, fb.FB_FORWARD, False, False)
-    b = run(batch, x, fb.FB_FORWARD, True, False)
-    assert np.array_equal(a, b)
-    c = run(batch, x, fb.FB_FORWARD, True, False)
-    assert np.array_equal(b, c)
+    for in_place in (False, True):
+        for direction in (fb.FB_FORWARD, fb.FB_INVERSE):
+            a = run(batch, x, direction, 0, in_place)
+            b = run(batch, x, direction, 1, in_place)
+            assert np.array_equal(a, b), (in_place, direction)
+            c = run(batch, x, direction, 2, in_place)
+            assert np.array_equal(a, c), (in_place, direction)
+    d = run(batch, x, fb.FB_FORWARD, 1, False)   # a second single launch on the same plan
+    assert np.array_equal(d, run(batch, x, fb.FB_FORWARD, 0, False))
 
 
 def test_batch_workload_4096_plus_64x512x512():
@@ -80,6 +90,8 @@ def test_batch_workload_4096_plus_64x512x512():
     and two 2D transforms, in both execution modes."""
     lens = inputs.batch_lengths(4096, 3).tolist()
     batch = fb.Batch(lens, n2d=64, side2d=512)
+    print("batch plan:", batch.description, flush=True)
+    assert "onelaunch=1" in batch.description   # the workload runs in one launch
     x = packed_input(batch, 3)
     first = {}
     last = {}
@@ -87,8 +99,10 @@ def test_batch_workload_4096_plus_64x512x512():
         first.setdefault(n, i)
         last[n] = i
     sample = sorted(set(first.values()) | set(last.values())) + [4096, 4096 + 63]
-    for persistent in (False, True):
+    outs = []
+    for persistent in MODES:
         got = run(batch, x, fb.FB_FORWARD, persistent, False)
+        outs.append(got)
         worst = 0.0
         for i in sample:
             o = batch.offsets[i]
@@ -98,6 +112,7 @@ def test_batch_workload_4096_plus_64x512x512():
             assert e < TOL, (persistent, i, n, e)
         print(f"batch workload persistent={persistent}: {len(sample)} transforms checked, worst rel L2 {worst:.2e}",
               flush=True)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2]) and np.array_equal(outs[0], outs[2])
 
 
 @pytest.mark.parametrize("lens,n2d,side", [([], 2, 64), ([196608], 0, 0), ([2], 0, 0), ([3] * 5, 0, 0),
@@ -110,7 +125,7 @@ def test_batch_edge_shapes(lens, n2d, side):
     batch = fb.Batch(lens, n2d=n2d, side2d=side)
     x = packed_input(batch, 11)
     outs = []
-    for persistent in (False, True):
+    for persistent in MODES:
         got = run(batch, x, fb.FB_FORWARD, persistent, False)
         for i in range(len(lens) + n2d):
             o = batch.offsets[i]
@@ -118,4 +133,4 @@ def test_batch_edge_shapes(lens, n2d, side):
             e = rel_l2(got[o:o + n].astype(np.complex128), ref_transform(batch, x, i, fb.FB_FORWARD))
             assert e < TOL, (persistent, i, n, e)
         outs.append(got)
-    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
