@@ -78,7 +78,7 @@ int fb_describe_shape(int64_t nx, int64_t ny, int64_t nz, int dtype, char *buf, 
 
 /* Create a plan for an nx x ny x nz grid of the given dtype (section 3.4
  * B-1: the library and its usage method for this block).  Every axis length
- * must be 2^a or 3*2^a with 1 <= n <= 4096 (n = 1 skips that axis).  The plan
+ * must be 2^a 3^b with 1 <= n <= 4096 (n = 1 skips that axis).  The plan
  * owns small device tables (twiddles generated on the device in binary64, a
  * binary32 copy rounded from them); creation is synchronous.  Returns NULL on
  * error (see fb_last_error). */
@@ -211,7 +211,7 @@ fb_status fb_lu_factor(double *a, int64_t n, int64_t lda, int32_t *ipiv, int32_t
 /* ---- Batched form ------------------------------------------------------
  * Many independent complex64 transforms in one call: n1d 1D transforms of
  * lengths lens[0..n1d) (each 2^a or 3*2^a, 2 <= n <= 2^21) and n2d 2D
- * transforms of side2d x side2d (side2d a supported 3D axis length), packed
+ * transforms of side2d x side2d (side2d = 2^a or 3*2^a, up to 4096), packed
  * back to back in one buffer in that order (fb_batch_offsets gives each
  * start).  Forward transforms are unscaled; inverse ones divide by the
  * transform size.  Lengths up to 4096 take one pencil pass; longer 1D

@@ -124,7 +124,7 @@ int check_shape(int64_t nx, int64_t ny, int64_t nz, int dtype)
         if (d[i] < 1) return fail(FB_ERR_INVALID_ARG, "%s = %lld must be >= 1", nm[i], (long long)d[i]);
         if (!fb::supported_length(d[i]))
             return fail(FB_ERR_UNSUPPORTED_SIZE,
-                        "%s = %lld is not supported (axis lengths must be 2^a or 3*2^a, 1..4096)", nm[i],
+                        "%s = %lld is not supported (axis lengths must be 2^a 3^b, 1..4096)", nm[i],
                         (long long)d[i]);
     }
     return FB_OK;
@@ -384,6 +384,12 @@ int fb_describe_shape(int64_t nx, int64_t ny, int64_t nz, int dtype, char *buf, 
     if (!buf || cap <= 0) return fail(FB_ERR_INVALID_ARG, "buf is NULL or cap <= 0");
     AxisPlan ax[3];
     build_axes(nx, ny, nz, esize_of(dtype), dtype == FB_C64_SPLITBF16, ax);
+    // the host-side lookup must find an instantiated pass for every axis
+    // (the same lookup fb_fft3d_plan makes; no device needed)
+    for (int a = 0; a < 3; a++)
+        if (ax[a].n > 1 && (!ax[a].pass.launch || ax[a].pass.pencils_per_wg < 1))
+            return fail(FB_ERR_UNSUPPORTED_SIZE, "internal: no pass instantiated for length %lld",
+                        (long long)ax[a].n);
     char tmp[256];
     describe(ax, tmp, sizeof tmp);
     const int len = (int)strlen(tmp);
@@ -811,11 +817,11 @@ void batch_split(int64_t n, int64_t &n1, int64_t &n2)
 
 bool batch_length_ok(int64_t n)
 {
-    if (fb::supported_length(n)) return n >= 2;
+    if (fb::supported_length_b1(n)) return n >= 2;
     if (n <= 4096 || n > 4096 * 512) return false;
     int64_t n1, n2;
     batch_split(n, n1, n2);
-    return n1 * n2 == n && fb::supported_length(n1) && fb::supported_length(n2) && n1 >= 2 && n2 >= 2;
+    return n1 * n2 == n && fb::supported_length_b1(n1) && fb::supported_length_b1(n2) && n1 >= 2 && n2 >= 2;
 }
 
 template <class T> T *dev_alloc(fb_batch *b, size_t count, hipError_t &e)
@@ -846,6 +852,17 @@ void set_geom(PassArgs &a, int64_t npencils, int64_t segp, const int64_t *seg_of
 }
 
 int64_t gcd64(int64_t a, int64_t b) { return b == 0 ? a : gcd64(b, a % b); }
+
+// Pencils per tile of an instantiated pass; 1 (and `bad` set) when the
+// length has no pass, so that no tile count divides by zero.
+int tile_pencils_of(const PassInfo &pi, bool &bad)
+{
+    if (!pi.launch || pi.pencils_per_wg < 1) {
+        bad = true;
+        return 1;
+    }
+    return pi.pencils_per_wg;
+}
 
 // Smallest number of consecutive segments (transforms) of a group that its
 // tiles cover exactly: tiles hold tile_pencils pencils and start at pencil 0.
@@ -973,7 +990,7 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
                  (long long)lens[i], i);
             return nullptr;
         }
-    if (n2d > 0 && (side2d < 2 || !fb::supported_length(side2d))) {
+    if (n2d > 0 && (side2d < 2 || !fb::supported_length_b1(side2d))) {
         fail(FB_ERR_UNSUPPORTED_SIZE, "2D side %lld is not supported", (long long)side2d);
         return nullptr;
     }
@@ -1039,6 +1056,7 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
     (void)scratch64;
 
     std::vector<fb::BatchGroup> pass1, single, pass2;
+    bool nopass = false;   // a pass length without an instantiated pass (not expected)
     auto new_group = [&](int64_t n, bool contig) {
         fb::BatchGroup g{};
         g.n = (int)n;
@@ -1064,7 +1082,7 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
             g.out_sel = 1;
             g.last = 1;
             g.inv_scale = 1.0 / (double)L;
-            g.tile_pencils = fb::find_pass(esize, (int)L, true, false).pencils_per_wg;
+            g.tile_pencils = tile_pencils_of(fb::find_pass(esize, (int)L, true, false), nopass);
             g.ntiles = (cnt + g.tile_pencils - 1) / g.tile_pencils;
             if (!group_in_bounds(g, segmax, b->total)) e = hipErrorInvalidValue;
             single.push_back(g);
@@ -1082,7 +1100,7 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
             g1.in_sel = 0;
             g1.out_sel = 2;   // fixed up per execution when out != in
             g1.last = 0;
-            const int P1 = fb::find_pass_pair((int)n1).pencils_per_wg;
+            const int P1 = tile_pencils_of(fb::find_pass_pair((int)n1), nopass);
             g1.ntiles = (cnt * n2 + P1 - 1) / P1;
             // a tile's outputs (pencils b .. b + P1 - 1 of one transform) form one
             // block of P1 n1 elements: write it whole when tiles do not straddle
@@ -1106,7 +1124,7 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
             g2.out_sel = 1;
             g2.last = 1;
             g2.inv_scale = 1.0 / (double)L;
-            const int P2 = fb::find_pass_pair((int)n2).pencils_per_wg;
+            const int P2 = tile_pencils_of(fb::find_pass_pair((int)n2), nopass);
             g2.ntiles = (cnt * n1 + P2 - 1) / P2;
             g2.tile_pencils = P2;
             // the pass-2 kernel reads the pre-twiddle table at the element's offset
@@ -1131,9 +1149,8 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
         set_geom(rows.args, n2d * s, s, soff, 1, s, 0, 1);
         rows.in_sel = 0;
         rows.out_sel = 1;
-        rows.ntiles = (n2d * s + fb::find_pass(esize, (int)s, true, false).pencils_per_wg - 1) /
-                      fb::find_pass(esize, (int)s, true, false).pencils_per_wg;
-        rows.tile_pencils = fb::find_pass(esize, (int)s, true, false).pencils_per_wg;
+        rows.tile_pencils = tile_pencils_of(fb::find_pass(esize, (int)s, true, false), nopass);
+        rows.ntiles = (n2d * s + rows.tile_pencils - 1) / rows.tile_pencils;
         cols = new_group(s, false);
         set_geom(cols.args, n2d * s, s, soff, s, 0, 1, s);
         cols.in_sel = 1;
@@ -1141,14 +1158,14 @@ fb_batch *fb_batch_plan(const int64_t *lens, int n1d, int n2d, int64_t side2d, i
         cols.last = 1;
         cols.phase = 1;
         cols.inv_scale = 1.0 / (double)(s * s);
-        cols.ntiles = (n2d * s + fb::find_pass_pair((int)s).pencils_per_wg - 1) /
-                      fb::find_pass_pair((int)s).pencils_per_wg;
-        cols.tile_pencils = fb::find_pass_pair((int)s).pencils_per_wg;
+        cols.tile_pencils = tile_pencils_of(fb::find_pass_pair((int)s), nopass);
+        cols.ntiles = (n2d * s + cols.tile_pencils - 1) / cols.tile_pencils;
         if (e == hipSuccess && (!group_in_bounds(rows, o2.back(), b->total) || !group_in_bounds(cols, o2.back(), b->total)))
             e = hipErrorInvalidValue;
     }
+    if (e == hipSuccess && nopass) e = hipErrorInvalidValue;
     if (e != hipSuccess) {
-        if (e == hipErrorInvalidValue) fail(FB_ERR_INVALID_ARG, "internal: batch geometry out of bounds");
+        if (e == hipErrorInvalidValue) fail(FB_ERR_INVALID_ARG, "internal: batch geometry out of bounds or no pass");
         else hip_fail(e, "batch plan");
         batch_free(b);
         delete b;

@@ -802,13 +802,54 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
     }
 }
 
+// Tile of workgroup b of a grid of nb workgroups.  The dispatcher deals
+// workgroups to the 8 XCDs (each with its own L2) round robin, so workgroup b
+// runs on XCD b mod 8; with REMAP the tiles are renumbered so that each XCD
+// takes one contiguous run of tiles (consecutive tiles on one XCD share L2
+// lines and DRAM pages at the tile edges).  A bijection on [0, nb).
+// Measured per pass kind on MI355X (512x256x256): the strided complex64
+// matrix-core passes gain (with half-size tiles, 36 KB, the 256-point pass
+// 117 -> 107 us), the complex128 passes lose (the 512-point x pass 201 ->
+// 217 us), so it is a per-kind build knob.
+#ifndef FB_XCD_REMAP
+#define FB_XCD_REMAP 0               // every pass
+#endif
+#ifndef FB_XCD_REMAP_MX_STRIDED
+#define FB_XCD_REMAP_MX_STRIDED 1    // strided matrix-core passes
+#endif
+constexpr int kXcds = 8;
+template <bool REMAP> __device__ __forceinline__ int64_t tile_of_block(int64_t b, int64_t nb)
+{
+    if constexpr (!REMAP) {
+        (void)nb;
+        return b;
+    } else {
+        const int64_t q = nb / kXcds, r = nb % kXcds;
+        const int64_t x = b % kXcds, i = b / kXcds;
+        return x * q + (x < r ? x : r) + i;
+    }
+}
+// Strided tiles whose row segment (P adjacent pencils) is narrower than an
+// L2 line share lines with their neighbours: those are remapped too
+// (FB_XCD_REMAP_NARROW).
+#ifndef FB_XCD_REMAP_NARROW
+#define FB_XCD_REMAP_NARROW 1
+#endif
+template <typename V, int N, bool CONTIG, bool MX> constexpr bool xcd_remap()
+{
+    constexpr int seg_bytes = PassCfg<V, N, CONTIG, MX>::P * (int)sizeof(V);
+    return FB_XCD_REMAP || (FB_XCD_REMAP_MX_STRIDED && MX && !CONTIG) ||
+           (FB_XCD_REMAP_NARROW && !CONTIG && seg_bytes < 128);
+}
+
 template <typename V, int N, bool CONTIG, bool MX>
 __global__ void __launch_bounds__((PassCfg<V, N, CONTIG, MX>::THREADS)) FB_OCCUPANCY fft_pass(PassArgs a)
 {
     using Cfg = PassCfg<V, N, CONTIG, MX>;
     __shared__ typename Cfg::LdsT lds[Cfg::P * Cfg::LS];
     __shared__ real_t<V> gtab[CONTIG ? N : 1];
-    pass_tile<V, N, CONTIG, MX>(a, blockIdx.x, threadIdx.x, (V *)lds, gtab);
+    pass_tile<V, N, CONTIG, MX>(a, tile_of_block<xcd_remap<V, N, CONTIG, MX>()>(blockIdx.x, gridDim.x), threadIdx.x,
+                                (V *)lds, gtab);
 }
 
 // Contiguous evolve pass with several outputs: the tile's spectrum is read
@@ -820,7 +861,8 @@ __global__ void __launch_bounds__((PassCfg<V, N, true, MX>::THREADS)) FB_OCCUPAN
     using Cfg = PassCfg<V, N, true, MX>;
     __shared__ typename Cfg::LdsT lds[Cfg::P * Cfg::LS];
     __shared__ real_t<V> gtab[N];
-    pass_tile<V, N, true, MX, true>(a, blockIdx.x, threadIdx.x, (V *)lds, gtab);
+    pass_tile<V, N, true, MX, true>(a, tile_of_block<xcd_remap<V, N, true, MX>()>(blockIdx.x, gridDim.x), threadIdx.x,
+                                    (V *)lds, gtab);
 }
 
 }  // namespace fb

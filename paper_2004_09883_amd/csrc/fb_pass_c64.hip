@@ -3,5 +3,10 @@
 #include "fb_pass_inst.hpp"
 
 namespace fb {
-PassInfo find_pass_c64(int n, bool contig, bool mx) { return find_pass_t<float2>(n, contig, mx); }
+PassInfo find_pass3_c64(int n, bool contig, bool mx);
+PassInfo find_pass_c64(int n, bool contig, bool mx)
+{
+    const PassInfo r = find_pass_t<float2, FB_LIST_B3>(n, contig, mx);
+    return r.launch ? r : find_pass3_c64(n, contig, mx);
+}
 }  // namespace fb

@@ -1,6 +1,7 @@
 // fb_pass_inst.hpp -- instantiates the pencil passes of one element type for
-// every supported axis length (2^a and 3*2^a up to 4096) and builds the
-// length -> launcher table.
+// a list of axis lengths (2^a and 3*2^a up to 4096, or with FB_LENGTHS_3B
+// the lengths 2^a 3^b, b >= 2, up to 4096) and builds the length ->
+// launcher table.
 #pragma once
 #include "fb_internal.hpp"
 #include "fb_pass.hpp"
@@ -34,9 +35,28 @@ template <typename V, int N> PassInfo pass_info(bool contig, bool mx)
     return contig ? pass_info_k<V, N, true>(mx) : pass_info_k<V, N, false>(mx);
 }
 
+// Axis lengths 2^a and 3 * 2^a up to 4096 (the list the batched form and
+// the other translation units share) ...
 #define FB_FOR_EACH_LENGTH(X) \
     X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) \
     X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096)
+// ... and 2^a 3^b with b >= 2 up to 4096, instantiated in translation units
+// of their own (fb_pass3_*.hip, fb_steps3_*.hip) so that both halves compile
+// in parallel.
+#define FB_FOR_EACH_LENGTH_3B(X) \
+    X(9) X(18) X(36) X(72) X(144) X(288) X(576) X(1152) X(2304) \
+    X(27) X(54) X(108) X(216) X(432) X(864) X(1728) X(3456) \
+    X(81) X(162) X(324) X(648) X(1296) X(2592) \
+    X(243) X(486) X(972) X(1944) X(3888) \
+    X(729) X(1458) X(2916) X(2187)
+// The lookup functions below take the list as a template argument (B3), so
+// that the two halves are distinct instantiations rather than one inline
+// function with two bodies.
+#ifdef FB_LENGTHS_3B
+#define FB_LIST_B3 true
+#else
+#define FB_LIST_B3 false
+#endif
 
 // Strided complex64 passes over pencil pairs (16-byte accesses); MX selects
 // the matrix-core radix-16 variant where one exists.
@@ -50,14 +70,15 @@ template <int N> PassInfo pass_info_pair(bool mx)
     return {&launch_pass<c2x, N, false, false>, 2 * Cfg::P, Cfg::THREADS, 0};
 }
 
-inline PassInfo find_pass_pair_t(int n, bool mx)
+template <bool B3> PassInfo find_pass_pair_t(int n, bool mx)
 {
-    switch (n) {
 #define FB_CASE(L) case L: return pass_info_pair<L>(mx);
-        FB_FOR_EACH_LENGTH(FB_CASE)
-#undef FB_CASE
-    default: return {nullptr, 0, 0, 0};
+    if constexpr (B3) {
+        switch (n) { FB_FOR_EACH_LENGTH_3B(FB_CASE) default: return {nullptr, 0, 0, 0}; }
+    } else {
+        switch (n) { FB_FOR_EACH_LENGTH(FB_CASE) default: return {nullptr, 0, 0, 0}; }
     }
+#undef FB_CASE
 }
 
 template <typename V, int N, bool MX> hipError_t launch_pass_multi(const PassArgs &a, hipStream_t st)
@@ -81,24 +102,26 @@ template <typename V, int N> PassInfo pass_info_multi(bool mx)
     return {&launch_pass_multi<V, N, false>, Cfg::P, Cfg::THREADS, 0};
 }
 
-template <typename V> PassInfo find_pass_multi_t(int n, bool mx)
+template <typename V, bool B3> PassInfo find_pass_multi_t(int n, bool mx)
 {
-    switch (n) {
 #define FB_CASE(L) case L: return pass_info_multi<V, L>(mx);
-        FB_FOR_EACH_LENGTH(FB_CASE)
-#undef FB_CASE
-    default: return {nullptr, 0, 0, 0};
+    if constexpr (B3) {
+        switch (n) { FB_FOR_EACH_LENGTH_3B(FB_CASE) default: return {nullptr, 0, 0, 0}; }
+    } else {
+        switch (n) { FB_FOR_EACH_LENGTH(FB_CASE) default: return {nullptr, 0, 0, 0}; }
     }
+#undef FB_CASE
 }
 
-template <typename V> PassInfo find_pass_t(int n, bool contig, bool mx)
+template <typename V, bool B3> PassInfo find_pass_t(int n, bool contig, bool mx)
 {
-    switch (n) {
 #define FB_CASE(L) case L: return pass_info<V, L>(contig, mx);
-        FB_FOR_EACH_LENGTH(FB_CASE)
-#undef FB_CASE
-    default: return {nullptr, 0, 0, 0};
+    if constexpr (B3) {
+        switch (n) { FB_FOR_EACH_LENGTH_3B(FB_CASE) default: return {nullptr, 0, 0, 0}; }
+    } else {
+        switch (n) { FB_FOR_EACH_LENGTH(FB_CASE) default: return {nullptr, 0, 0, 0}; }
     }
+#undef FB_CASE
 }
 
 }  // namespace fb

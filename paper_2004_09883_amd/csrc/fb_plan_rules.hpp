@@ -3,8 +3,8 @@
 //
 // Radix list of n = 2^a 3^b, in the order the stages are applied to the data:
 // b threes, then floor(a/4) sixteens, then 2^(a mod 4) when a mod 4 > 0
-// (e.g. 512 -> 16,16,2; 768 -> 3,16,16; 64 -> 16,4).  The library supports
-// b <= 1 (n = 2^a or 3*2^a) and n <= 4096 on a 3D axis.
+// (e.g. 512 -> 16,16,2; 768 -> 3,16,16; 64 -> 16,4; 2304 -> 3,3,16,16).
+// A 3D axis may have any such length up to 4096.
 #pragma once
 #include <stdint.h>
 
@@ -40,8 +40,18 @@ constexpr RadixPlan radix_plan(int n)
     return p;
 }
 
-// True when n is an axis length the 3D passes support.
+// True when n is an axis length the 3D passes support: 2^a 3^b, 1..4096.
 constexpr bool supported_length(int64_t n)
+{
+    if (n < 1 || n > 4096) return false;
+    int64_t m = n;
+    while (m % 3 == 0) m /= 3;
+    while (m % 2 == 0) m /= 2;
+    return m == 1;
+}
+
+// True for the lengths 2^a and 3 * 2^a (the batched form's pass lengths).
+constexpr bool supported_length_b1(int64_t n)
 {
     if (n < 1 || n > 4096) return false;
     int64_t m = n;
@@ -50,8 +60,11 @@ constexpr bool supported_length(int64_t n)
     return m == 1;
 }
 
-// Threads that cooperate on one pencil: each holds about 16 elements.
-constexpr int threads_per_pencil(int n) { return (n % 16 == 0) ? n / 16 : 1; }
+// Threads that cooperate on one pencil: each holds about 16 elements (n/16
+// threads when 16 divides n; one thread for the short lengths up to 32;
+// otherwise ceil(n/16), and the stages whose butterfly count is not a
+// multiple of it leave the last round part-filled).
+constexpr int threads_per_pencil(int n) { return (n % 16 == 0) ? n / 16 : n <= 32 ? 1 : (n + 15) / 16; }
 
 // Largest number of elements one thread holds over all stages.
 constexpr int regs_per_thread(int n)
@@ -103,6 +116,9 @@ constexpr int lds_pencil_stride(int n)
 #ifndef FB_LDS_STRIDED_KB
 #define FB_LDS_STRIDED_KB 72
 #endif
+#ifndef FB_LDS_STRIDED_MX_KB
+#define FB_LDS_STRIDED_MX_KB 36   // strided complex64 matrix-core passes: half-size tiles
+#endif
 #ifndef FB_STRIDED_P16
 #define FB_STRIDED_P16 16   // target pencils per workgroup, strided complex128
 #endif
@@ -115,7 +131,7 @@ constexpr int lds_pencil_stride(int n)
 
 constexpr int lds_budget_bytes(bool contig, int esize, bool mx = false)
 {
-    return !contig     ? FB_LDS_STRIDED_KB * 1024
+    return !contig     ? (mx ? FB_LDS_STRIDED_MX_KB : FB_LDS_STRIDED_KB) * 1024
            : esize == 16 ? FB_LDS_CONTIG16_KB * 1024
            : mx          ? FB_LDS_CONTIG_MX_KB * 1024
                          : FB_LDS_CONTIG_KB * 1024;

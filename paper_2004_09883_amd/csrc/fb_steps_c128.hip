@@ -3,5 +3,10 @@
 #include "fb_pass_inst.hpp"
 
 namespace fb {
-PassInfo find_pass_multi_c128(int n) { return find_pass_multi_t<double2>(n, false); }
+PassInfo find_pass3_multi_c128(int n);
+PassInfo find_pass_multi_c128(int n)
+{
+    const PassInfo r = find_pass_multi_t<double2, FB_LIST_B3>(n, false);
+    return r.launch ? r : find_pass3_multi_c128(n);
+}
 }  // namespace fb

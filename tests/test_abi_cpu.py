@@ -35,7 +35,8 @@ def test_version():
 
 
 SHAPES = [(512, 256, 256), (256, 256, 128), (64, 64, 64), (32, 32, 32), (128, 256, 512), (1, 512, 512),
-          (1, 1, 1), (3, 6, 12), (4096, 2, 1), (768, 96, 24), (1, 3072, 48), (2, 1, 1536)]
+          (1, 1, 1), (3, 6, 12), (4096, 2, 1), (768, 96, 24), (1, 3072, 48), (2, 1, 1536),
+          (9, 27, 81), (2187, 1, 18), (2304, 3456, 3888), (729, 1458, 2916), (144, 36, 2592)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -44,10 +45,34 @@ def test_describe_matches_oracle(shape):
         assert fb.fb_describe_shape(*shape, dt) == oracle.describe(*shape)
 
 
+def _is_2a3b(n):
+    while n % 2 == 0:
+        n //= 2
+    while n % 3 == 0:
+        n //= 3
+    return n == 1
+
+
+ALL_LENGTHS = [n for n in range(2, 4097) if _is_2a3b(n)]
+
+
+def test_every_supported_length_has_a_pass_on_every_axis():
+    """Every axis length 2^a 3^b up to 4096 (55 of them) describes on every
+    axis and in every dtype: the host-side lookup finds an instantiated pass
+    (the lookup a plan makes), and the radix list equals the oracle's."""
+    assert len(ALL_LENGTHS) == 55
+    for n in ALL_LENGTHS:
+        for shape in ((1, 1, n), (1, n, 2), (n, 2, 1)):
+            for dt in (fb.FB_C128, fb.FB_C64, fb.FB_C64_SPLITBF16):
+                assert fb.fb_describe_shape(*shape, dt) == oracle.describe(*shape), (shape, dt)
+
+
 @pytest.mark.parametrize("shape,code", [((0, 4, 4), fb.FB_ERR_INVALID_ARG), ((4, -1, 4), fb.FB_ERR_INVALID_ARG),
                                         ((5, 4, 4), fb.FB_ERR_UNSUPPORTED_SIZE),
                                         ((4, 4, 8192), fb.FB_ERR_UNSUPPORTED_SIZE),
-                                        ((4, 9, 4), fb.FB_ERR_UNSUPPORTED_SIZE),
+                                        ((4, 7, 4), fb.FB_ERR_UNSUPPORTED_SIZE),
+                                        ((4, 4, 6561), fb.FB_ERR_UNSUPPORTED_SIZE),
+                                        ((10, 4, 4), fb.FB_ERR_UNSUPPORTED_SIZE),
                                         ((4, 4, 6144), fb.FB_ERR_UNSUPPORTED_SIZE)])
 def test_describe_rejects_shapes(shape, code):
     with pytest.raises(fb.FbError) as e:

@@ -21,6 +21,9 @@ torch = pytest.importorskip("torch")
 TOL = {fb.FB_C128: 1e-12, fb.FB_C64: 1e-5, fb.FB_C64_SPLITBF16: 1e-5}
 DTYPES = [fb.FB_C128, fb.FB_C64, fb.FB_C64_SPLITBF16]
 LENGTHS = [2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096]
+# 2^a 3^b with b >= 2 (repeated radix-3 stages), every one up to 4096
+LENGTHS_3B = [9, 18, 36, 72, 144, 288, 576, 1152, 2304, 27, 54, 108, 216, 432, 864, 1728, 3456, 81, 162, 324, 648,
+              1296, 2592, 243, 486, 972, 1944, 3888, 729, 1458, 2916, 2187]
 
 
 def rel_l2(a, b):
@@ -71,7 +74,7 @@ def run_fft(shape, dtype, seed=1, direction=fb.FB_FORWARD, inplace=False):
 # ---------------------------------------------------------------- one axis at a time
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("n", LENGTHS)
+@pytest.mark.parametrize("n", LENGTHS + LENGTHS_3B)
 @pytest.mark.parametrize("axis", ["z", "y", "x"])
 def test_single_axis_pass(axis, n, dtype):
     shape = {"z": (1, 3, n), "y": (2, n, 6), "x": (n, 3, 4)}[axis]
@@ -86,7 +89,9 @@ def test_single_axis_pass(axis, n, dtype):
 SHAPES_3D = [(64, 64, 64), (32, 48, 96), (12, 96, 24), (3, 6, 12), (1, 1, 1), (1, 1, 4096), (4096, 1, 2),
              (2, 4096, 1), (128, 256, 512), (256, 256, 128),
              # pencil counts that leave a part-filled last tile on every axis
-             (3, 3, 256), (3, 256, 3), (256, 3, 3), (6, 3, 96)]
+             (3, 3, 256), (3, 256, 3), (256, 3, 3), (6, 3, 96),
+             # repeated radix-3 stages on every axis
+             (9, 27, 36), (18, 81, 54), (144, 9, 2304)]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -355,6 +360,13 @@ def test_block_part_filled_tiles(shape, dtype):
 def test_block_c64(dtype):
     check_block((64, 64, 64), dtype, seed=1, alpha=1e-6, steps=6)
     check_block((128, 64, 96), dtype, seed=2, alpha=1e-6, steps=3, gaussian=True)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_block_lengths_with_repeated_threes(dtype):
+    """A spectral block whose axes have two or more radix-3 stages
+    (36 = 3.3.4, 144 = 3.3.16, 27 = 3.3.3)."""
+    check_block((36, 144, 27), dtype, seed=4, alpha=1e-4, steps=3)
 
 
 def test_precision_forms_512x256x256():
