@@ -191,8 +191,18 @@ struct fb_plan {
     float2 *tw32;
     size_t tw_total;
     int device;
+    // non-temporal accesses for every pass, whatever the grid's size (set by
+    // the serving loop, whose concurrent requests share the last-level cache)
+    bool nt_always = false;
     char desc[256];
 };
+
+namespace fb {
+void plan_set_nt_always(fb_plan *p, bool on)
+{
+    if (p) p->nt_always = on;
+}
+}  // namespace fb
 
 namespace {
 
@@ -286,7 +296,7 @@ int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, dou
     }
     args.inv = inv;
     args.scale = scale;
-    args.nt = (double)ngrids * (double)p->N * (double)p->esize >= (double)FB_NT_MIN_BYTES ? 1 : 0;
+    args.nt = (p->nt_always || (double)ngrids * (double)p->N * (double)p->esize >= (double)FB_NT_MIN_BYTES) ? 1 : 0;
     if (ev) {
         args.evolve = 1;
         args.ev_c = ev->ev_c;
@@ -311,7 +321,8 @@ int launch_axis(const fb_plan *p, int a, const void *in, void *out, int inv, dou
     const double reads = gen_seed ? 0.0 : 1.0;
     const double writes = multi ? (double)multi->nout : 1.0;
     const double bytes = (reads + writes) * (double)ngrids * (double)p->N * (double)p->esize;
-    hipError_t e = timed_launch(name, bytes, st, [&] { return pi.launch(args, st); });
+    const fb::PassLauncher launcher = pi.pick(args);
+    hipError_t e = timed_launch(name, bytes, st, [&] { return launcher(args, st); });
     if (e != hipSuccess) return hip_fail(e, "pass launch");
     return FB_OK;
 }
@@ -1363,7 +1374,8 @@ fb_status fb_batch_exec(const fb_batch *b, const void *in, void *out, void *work
         const PassInfo pi = g.contig ? fb::find_pass(8, g.n, true, false) : fb::find_pass_pair(g.n);
         char name[96];
         snprintf(name, sizeof name, "fft_pass<c64,n=%d,%s>", g.n, g.contig ? "contiguous" : "strided,pairs");
-        e = timed_launch(name, 0.0, st, [&] { return pi.launch(a, st); });
+        const fb::PassLauncher launcher = pi.pick(a);
+        e = timed_launch(name, 0.0, st, [&] { return launcher(a, st); });
         if (e != hipSuccess) return (fb_status)hip_fail(e, "batch pass launch");
     }
     return (fb_status)ok();

@@ -44,8 +44,9 @@ struct PassArgs {
     // instead of a load from `in`
     int gen;
     uint64_t gen_seed;
-    // non-temporal global accesses allowed (for the pass kinds that gain from
-    // them): set when the data the pass sweeps exceeds the last-level cache
+    // non-temporal global accesses wanted (the host then launches the pass
+    // kind's non-temporal instance, where it has one): set when the data the
+    // pass sweeps exceeds the last-level cache
     int nt;
     int inv;            // 1: inverse (conjugate on load and on store)
     double scale;       // applied on store (1/N in the last inverse pass)
@@ -79,6 +80,10 @@ struct PassInfo {
     int pencils_per_wg;
     int threads;
     int mx;   // 1 when the radix-16 stages run on the matrix cores
+    // the same pass with non-temporal global accesses (nullptr when the pass
+    // kind has none); launched instead when PassArgs::nt is set
+    PassLauncher launch_nt = nullptr;
+    PassLauncher pick(const PassArgs &a) const { return (a.nt && launch_nt) ? launch_nt : launch; }
 };
 
 // esize: 16 (complex128) or 8 (complex64); mx asks for the matrix-core
@@ -117,6 +122,15 @@ hipError_t launch_evolve(int esize, const void *in, void *out, int64_t nx, int64
 // out2[0] + i out2[1] = sum_{j<1024} x[(17 j) mod N], fixed-order binary64 tree.
 // Checksums of `count` consecutive grids of N elements into out2[2g], out2[2g+1].
 hipError_t launch_checksum(int esize, const void *x, int64_t N, double *out2, hipStream_t st, int count = 1);
+
+}  // namespace fb
+struct fb_plan;
+namespace fb {
+// Make every pass of the plan use non-temporal global accesses (where the
+// pass kind gains from them) whatever the grid's size: for callers that run
+// many requests at once, whose grids together exceed the last-level cache.
+// Call before the plan is used.
+void plan_set_nt_always(fb_plan *p, bool on);
 
 // Device address of the current device's copy of the static staging buffer
 // (FB_STATIC_SCRATCH_BYTES), looked up once per device and cached.

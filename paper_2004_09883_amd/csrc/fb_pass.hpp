@@ -78,11 +78,16 @@ template <typename V, int N, bool CONTIG> constexpr bool mx_capable()
 //    up to 40 % slower: their 256 MiB grids partly stay in the 256 MB
 //    last-level cache between passes, which non-temporal accesses give up.
 // The choice is per pass kind, with build-time knobs, and per launch: the
-// host sets PassArgs::nt only when the data a pass sweeps is larger than
-// the last-level cache (FB_NT_MIN_BYTES), since a grid that fits it (the
-// 128 MiB 256x256x128 complex128 block, the 64 MiB 2048x2048 one) gains
-// from the cache between passes: that block took 2.96 ms per 20 steps with
-// non-temporal accesses against 2.69 ms without.
+// kinds above are instantiated twice (template argument NT), and the host
+// launches the non-temporal instance only when the data a pass sweeps is
+// larger than the last-level cache (FB_NT_MIN_BYTES), since a grid that fits
+// it (the 128 MiB 256x256x128 complex128 block, the 64 MiB 2048x2048 one)
+// gains from the cache between passes: that block took 2.96 ms per 20 steps
+// with non-temporal accesses against 2.69 ms without.  (A branch on a
+// kernel argument instead of two instances made every pass carry both
+// versions of its loads and stores; in the serving mix, where many pass
+// kernels run at once, that alone raised the service p50 from 2.50 to
+// 2.84 ms and the end-to-end p50 from 16 to 48 ms.)
 #ifndef FB_NT_C128_CONTIG
 #define FB_NT_C128_CONTIG 1
 #endif
@@ -313,7 +318,7 @@ struct MxGlobalOut {
 // writes the tile's block of P x N elements with consecutive threads on
 // consecutive elements.  On entry the LDS rows are free (the last stage has
 // read its inputs and passed a barrier).
-template <typename V, int N, bool CONTIG, int M>
+template <typename V, int N, bool CONTIG, bool NT, int M>
 __device__ __forceinline__ void store_tile_contiguous(const PassArgs &a, int64_t tile, int tid, bool active,
                                                       bool valid, int t, V *row, V *lds, const V (&v)[M])
 {
@@ -356,19 +361,18 @@ __device__ __forceinline__ void store_tile_contiguous(const PassArgs &a, int64_t
         const int count = (int)np * N;
         elem_t<V> *o = (elem_t<V> *)a.out + ob;
         auto store_all = [&](auto ntc) {
-            constexpr bool NT = decltype(ntc)::value;
+            constexpr bool NTA = decltype(ntc)::value;
             for (int i = tid; i < count; i += Cfg::THREADS) {
                 const int j = i / N, k = i - (i / N) * N;
                 if constexpr (PAIR) {
                     const c2x &e = lds[(j >> 1) * LS + lds_pos(k)];
-                    st_stream<NT>(o + i, (j & 1) ? e.b : e.a);
+                    st_stream<NTA>(o + i, (j & 1) ? e.b : e.a);
                 } else {
-                    st_stream<NT>(o + i, lds[j * LS + lds_pos(k)]);
+                    st_stream<NTA>(o + i, lds[j * LS + lds_pos(k)]);
                 }
             }
         };
-        if (nt_store<V, CONTIG>() && a.nt) store_all(std::true_type{});
-        else store_all(std::false_type{});
+        store_all(std::integral_constant<bool, NT && nt_store<V, CONTIG>()>{});
     }
 }
 
@@ -382,7 +386,7 @@ __device__ __forceinline__ void store_tile_contiguous(const PassArgs &a, int64_t
 // `gtab` N reals (contiguous passes).  The caller may run the tile on a
 // workgroup larger than the tile's THREADS (the persistent batch kernel):
 // the extra threads only take part in the barriers.
-template <typename V, int N, bool CONTIG, bool MX, bool MULTI = false>
+template <typename V, int N, bool CONTIG, bool MX, bool MULTI = false, bool NT = false>
 __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int tid, V *lds, real_t<V> *gtab)
 {
     using Cfg = PassCfg<V, N, CONTIG, MX>;
@@ -456,13 +460,13 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
     // global loads, non-temporal when this pass kind gains from it and the
     // grid is larger than the last-level cache (PassArgs::nt)
     auto load_all = [&](auto ntc) {
-        constexpr bool NT = decltype(ntc)::value;
+        constexpr bool NTA = decltype(ntc)::value;
 #pragma unroll
         for (int u = 0; u < U0; u++) {
             const int b = t + T * u;
             if (NBF0 % T == 0 || b < NBF0) {
 #pragma unroll
-                for (int q = 0; q < R0; q++) v[u * R0 + q] = ld_v<NT, V>(gin + (int64_t)(b + q * NBF0) * S);
+                for (int q = 0; q < R0; q++) v[u * R0 + q] = ld_v<NTA, V>(gin + (int64_t)(b + q * NBF0) * S);
             }
         }
     };
@@ -477,10 +481,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                         v[u * R0 + q] = uniform_elem<V>(a.gen_seed, (uint64_t)(base + (int64_t)(b + q * NBF0) * S));
                 }
             }
-        } else if (nt_load<V, CONTIG>() && a.nt) {
-            load_all(std::true_type{});
         } else {
-            load_all(std::false_type{});
+            load_all(std::integral_constant<bool, NT && nt_load<V, CONTIG>()>{});
         }
     }
     if constexpr (MULTI) {
@@ -760,12 +762,12 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
         }
         if constexpr (!CONTIG && !MX && !Cfg::SPLIT) {
             if (a.otile) {   // uniform over the workgroup
-                store_tile_contiguous<V, N, CONTIG>(a, tile, tid, active, valid, t, row, lds, v);
+                store_tile_contiguous<V, N, CONTIG, NT>(a, tile, tid, active, valid, t, row, lds, v);
                 return;
             }
         }
         auto store_all = [&](auto ntc) {
-            constexpr bool NT = decltype(ntc)::value;
+            constexpr bool NTA = decltype(ntc)::value;
             const R sc = (R)a.scale;
             E *__restrict__ go = MULTI ? gout + rep * a.out_step : gout;
 #pragma unroll
@@ -779,19 +781,18 @@ __device__ __forceinline__ void pass_tile(const PassArgs &a, int64_t tile, int t
                         if (a.scale != 1.0) o = cscale(o, sc);
                         if constexpr (PAIR) {
                             if (a.opair_step) {   // the pair's outputs are not adjacent
-                                st_stream<NT>(go + (int64_t)(b + q * NBF) * OS, o.a);
-                                st_stream<NT>(go + (int64_t)(b + q * NBF) * OS + a.opair_step, o.b);
+                                st_stream<NTA>(go + (int64_t)(b + q * NBF) * OS, o.a);
+                                st_stream<NTA>(go + (int64_t)(b + q * NBF) * OS + a.opair_step, o.b);
                                 continue;
                             }
                         }
-                        st_v<NT, V>(go + (int64_t)(b + q * NBF) * OS, o);
+                        st_v<NTA, V>(go + (int64_t)(b + q * NBF) * OS, o);
                     }
                 }
             }
         };
         if (valid && !MX_OUT) {
-            if (nt_store<V, CONTIG>() && a.nt) store_all(std::true_type{});
-            else store_all(std::false_type{});
+            store_all(std::integral_constant<bool, NT && nt_store<V, CONTIG>()>{});
         }
     }
     };   // outputs
@@ -842,27 +843,30 @@ template <typename V, int N, bool CONTIG, bool MX> constexpr bool xcd_remap()
            (FB_XCD_REMAP_NARROW && !CONTIG && seg_bytes < 128);
 }
 
-template <typename V, int N, bool CONTIG, bool MX>
+// True when the pass kind has a non-temporal instance (NT = true).
+template <typename V, bool CONTIG> constexpr bool has_nt() { return nt_load<V, CONTIG>() || nt_store<V, CONTIG>(); }
+
+template <typename V, int N, bool CONTIG, bool MX, bool NT = false>
 __global__ void __launch_bounds__((PassCfg<V, N, CONTIG, MX>::THREADS)) FB_OCCUPANCY fft_pass(PassArgs a)
 {
     using Cfg = PassCfg<V, N, CONTIG, MX>;
     __shared__ typename Cfg::LdsT lds[Cfg::P * Cfg::LS];
     __shared__ real_t<V> gtab[CONTIG ? N : 1];
-    pass_tile<V, N, CONTIG, MX>(a, tile_of_block<xcd_remap<V, N, CONTIG, MX>()>(blockIdx.x, gridDim.x), threadIdx.x,
-                                (V *)lds, gtab);
+    pass_tile<V, N, CONTIG, MX, false, NT>(a, tile_of_block<xcd_remap<V, N, CONTIG, MX>()>(blockIdx.x, gridDim.x),
+                                           threadIdx.x, (V *)lds, gtab);
 }
 
 // Contiguous evolve pass with several outputs: the tile's spectrum is read
 // once and output j (evolution constant ev_cs[j]) is written at
 // out + j out_step, for j < nout.
-template <typename V, int N, bool MX>
+template <typename V, int N, bool MX, bool NT = false>
 __global__ void __launch_bounds__((PassCfg<V, N, true, MX>::THREADS)) FB_OCCUPANCY fft_pass_multi(PassArgs a)
 {
     using Cfg = PassCfg<V, N, true, MX>;
     __shared__ typename Cfg::LdsT lds[Cfg::P * Cfg::LS];
     __shared__ real_t<V> gtab[N];
-    pass_tile<V, N, true, MX, true>(a, tile_of_block<xcd_remap<V, N, true, MX>()>(blockIdx.x, gridDim.x), threadIdx.x,
-                                    (V *)lds, gtab);
+    pass_tile<V, N, true, MX, true, NT>(a, tile_of_block<xcd_remap<V, N, true, MX>()>(blockIdx.x, gridDim.x),
+                                        threadIdx.x, (V *)lds, gtab);
 }
 
 }  // namespace fb

@@ -8,14 +8,22 @@
 
 namespace fb {
 
-template <typename V, int N, bool CONTIG, bool MX> hipError_t launch_pass(const PassArgs &a, hipStream_t st)
+template <typename V, int N, bool CONTIG, bool MX, bool NT = false>
+hipError_t launch_pass(const PassArgs &a, hipStream_t st)
 {
     using Cfg = PassCfg<V, N, CONTIG, MX>;
     constexpr int64_t UNIT = std::is_same<V, c2x>::value ? 2 : 1;   // pencils per tile slot
     const int64_t blocks = (a.npencils + UNIT * Cfg::P - 1) / (UNIT * Cfg::P);
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((fft_pass<V, N, CONTIG, MX>), dim3((unsigned)blocks), dim3(Cfg::THREADS), 0, st, a);
+    hipLaunchKernelGGL((fft_pass<V, N, CONTIG, MX, NT>), dim3((unsigned)blocks), dim3(Cfg::THREADS), 0, st, a);
     return hipGetLastError();
+}
+
+// The non-temporal instance of a pass kind, where it has one.
+template <typename V, int N, bool CONTIG, bool MX> constexpr PassLauncher nt_launcher()
+{
+    if constexpr (has_nt<V, CONTIG>()) return &launch_pass<V, N, CONTIG, MX, true>;
+    else return nullptr;
 }
 
 // MX selects the matrix-core radix-16 variant where one exists (complex64);
@@ -25,9 +33,10 @@ template <typename V, int N, bool CONTIG> PassInfo pass_info_k(bool mx)
     using Cfg = PassCfg<V, N, CONTIG>;
     using CfgM = PassCfg<V, N, CONTIG, true>;
     if constexpr (mx_capable<V, N, CONTIG>()) {
-        if (mx) return {&launch_pass<V, N, CONTIG, true>, CfgM::P, CfgM::THREADS, 1};
+        if (mx)
+            return {&launch_pass<V, N, CONTIG, true>, CfgM::P, CfgM::THREADS, 1, nt_launcher<V, N, CONTIG, true>()};
     }
-    return {&launch_pass<V, N, CONTIG, false>, Cfg::P, Cfg::THREADS, 0};
+    return {&launch_pass<V, N, CONTIG, false>, Cfg::P, Cfg::THREADS, 0, nt_launcher<V, N, CONTIG, false>()};
 }
 
 template <typename V, int N> PassInfo pass_info(bool contig, bool mx)
@@ -65,9 +74,9 @@ template <int N> PassInfo pass_info_pair(bool mx)
     using Cfg = PassCfg<c2x, N, false>;
     using CfgM = PassCfg<c2x, N, false, true>;
     if constexpr (mx_capable<c2x, N, false>()) {
-        if (mx) return {&launch_pass<c2x, N, false, true>, 2 * CfgM::P, CfgM::THREADS, 1};
+        if (mx) return {&launch_pass<c2x, N, false, true>, 2 * CfgM::P, CfgM::THREADS, 1, nt_launcher<c2x, N, false, true>()};
     }
-    return {&launch_pass<c2x, N, false, false>, 2 * Cfg::P, Cfg::THREADS, 0};
+    return {&launch_pass<c2x, N, false, false>, 2 * Cfg::P, Cfg::THREADS, 0, nt_launcher<c2x, N, false, false>()};
 }
 
 template <bool B3> PassInfo find_pass_pair_t(int n, bool mx)
@@ -81,13 +90,18 @@ template <bool B3> PassInfo find_pass_pair_t(int n, bool mx)
 #undef FB_CASE
 }
 
-template <typename V, int N, bool MX> hipError_t launch_pass_multi(const PassArgs &a, hipStream_t st)
+template <typename V, int N, bool MX, bool NT = false> hipError_t launch_pass_multi(const PassArgs &a, hipStream_t st)
 {
     using Cfg = PassCfg<V, N, true, MX>;
     const int64_t blocks = (a.npencils + Cfg::P - 1) / Cfg::P;
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((fft_pass_multi<V, N, MX>), dim3((unsigned)blocks), dim3(Cfg::THREADS), 0, st, a);
+    hipLaunchKernelGGL((fft_pass_multi<V, N, MX, NT>), dim3((unsigned)blocks), dim3(Cfg::THREADS), 0, st, a);
     return hipGetLastError();
+}
+template <typename V, int N, bool MX> constexpr PassLauncher nt_launcher_multi()
+{
+    if constexpr (has_nt<V, true>()) return &launch_pass_multi<V, N, MX, true>;
+    else return nullptr;
 }
 
 // Contiguous multi-output evolve passes (the matrix-core variant where one
@@ -97,9 +111,9 @@ template <typename V, int N> PassInfo pass_info_multi(bool mx)
     using Cfg = PassCfg<V, N, true>;
     using CfgM = PassCfg<V, N, true, true>;
     if constexpr (mx_capable<V, N, true>()) {
-        if (mx) return {&launch_pass_multi<V, N, true>, CfgM::P, CfgM::THREADS, 1};
+        if (mx) return {&launch_pass_multi<V, N, true>, CfgM::P, CfgM::THREADS, 1, nt_launcher_multi<V, N, true>()};
     }
-    return {&launch_pass_multi<V, N, false>, Cfg::P, Cfg::THREADS, 0};
+    return {&launch_pass_multi<V, N, false>, Cfg::P, Cfg::THREADS, 0, nt_launcher_multi<V, N, false>()};
 }
 
 template <typename V, bool B3> PassInfo find_pass_multi_t(int n, bool mx)
