@@ -162,7 +162,7 @@ def test_headline_block_as_benchmarked():
     t = bench.time_replays(torch, blk.run, warmup=1, reps=2)
     del t
     sums = blk.sums.cpu().numpy()
-    last = host(blk.out if blk.schedule == "per_step" else blk.out[steps - 1])
+    last = host(blk.out if blk.schedule != "fused_steps" else blk.out[steps - 1])
     del blk
     torch.cuda.empty_cache()
     X0 = oracle.fft3d(x0, -1)
