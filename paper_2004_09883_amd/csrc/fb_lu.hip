@@ -4,10 +4,11 @@
 //
 // For each panel of LU_NB columns starting at column k:
 //   lu_panel  factors rows k..n-1 of the panel column by column (pivot =
-//             first row of largest magnitude, row swap inside the panel,
+//             first row of largest magnitude, row exchange inside the panel,
 //             scaling, rank-1 update of the panel's remaining columns); one
 //             workgroup holds the whole panel in registers, four rows per
-//             thread of 512, so n <= 2048;
+//             thread of 512, so n <= 2048, and exchanges rows by relabelling
+//             them;
 //   lu_swap_trsm  applies the panel's row swaps, in order, to every column
 //             outside the panel, then U12 = L11^-1 A12 for the columns right
 //             of it (one thread per column, L11 in LDS);
@@ -37,25 +38,16 @@ __global__ void lu_init(int32_t *info)
 
 // ---- pivot search within a wavefront
 //
-// A candidate is (magnitude, row); the larger magnitude wins and equal
-// magnitudes go to the smaller row, so every reduction order finds the first
-// row of largest magnitude.  The all-reduce over 64 lanes exchanges with the
-// lanes l ^ 1, l ^ 2 (DPP quad permutations), 7 - l within 8 and 15 - l
-// within 16 (DPP half-row and row mirrors), then with the same lane of the
-// row r ^ 1 and r ^ 2 (permlane16 / permlane32 swaps): each step pairs
-// disjoint halves of a group, so after six steps every lane holds the
-// wave's best candidate.
-__device__ __forceinline__ bool beats(double ob, int oi, double b, int i)
-{
-    return (ob > b) | ((ob == b) & (oi < i));   // no short circuit: selects, not branches
-}
-__device__ __forceinline__ void better(double &b, int &i, double ob, int oi)
-{
-    const bool t = beats(ob, oi, b, i);
-    b = t ? ob : b;
-    i = t ? oi : i;
-}
-
+// The pivot is the first row (smallest position) among those of largest
+// magnitude.  It is found in two reductions: the largest magnitude M, then
+// the smallest position among the candidates whose magnitude equals M, so
+// each step is a single max or min instead of a compare-and-select on
+// (magnitude, row) pairs.  Magnitudes are compared as binary64 values, so
+// ties are exact.  The all-reduce over 64 lanes exchanges with the lanes
+// l ^ 1, l ^ 2 (DPP quad permutations), 7 - l within 8 and 15 - l within 16
+// (DPP half-row and row mirrors), then with the same lane of the row r ^ 1
+// and r ^ 2 (permlane16 / permlane32 swaps): each step pairs disjoint halves
+// of a group, so after six steps every lane holds the wave's result.
 template <int CTRL> __device__ __forceinline__ int dpp_i(int x)
 {
     return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
@@ -84,14 +76,25 @@ template <int ROWS> __device__ __forceinline__ double row_partner_d(double x, in
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-__device__ __forceinline__ void wave_best(double &b, int &i, int lane)
+__device__ __forceinline__ double dmax(double x, double y) { return x > y ? x : y; }
+__device__ __forceinline__ int imin(int x, int y) { return x < y ? x : y; }
+__device__ __forceinline__ double wave_max(double x, int lane)
 {
-    better(b, i, dpp_d<0xB1>(b), dpp_i<0xB1>(i));     // quad_perm [1,0,3,2]: l ^ 1
-    better(b, i, dpp_d<0x4E>(b), dpp_i<0x4E>(i));     // quad_perm [2,3,0,1]: l ^ 2
-    better(b, i, dpp_d<0x141>(b), dpp_i<0x141>(i));   // row_half_mirror
-    better(b, i, dpp_d<0x140>(b), dpp_i<0x140>(i));   // row_mirror
-    better(b, i, row_partner_d<1>(b, lane), row_partner_i<1>(i, lane));
-    better(b, i, row_partner_d<2>(b, lane), row_partner_i<2>(i, lane));
+    x = dmax(x, dpp_d<0xB1>(x));     // quad_perm [1,0,3,2]: l ^ 1
+    x = dmax(x, dpp_d<0x4E>(x));     // quad_perm [2,3,0,1]: l ^ 2
+    x = dmax(x, dpp_d<0x141>(x));    // row_half_mirror
+    x = dmax(x, dpp_d<0x140>(x));    // row_mirror
+    x = dmax(x, row_partner_d<1>(x, lane));
+    return dmax(x, row_partner_d<2>(x, lane));
+}
+__device__ __forceinline__ int wave_min(int i, int lane)
+{
+    i = imin(i, dpp_i<0xB1>(i));
+    i = imin(i, dpp_i<0x4E>(i));
+    i = imin(i, dpp_i<0x141>(i));
+    i = imin(i, dpp_i<0x140>(i));
+    i = imin(i, row_partner_i<1>(i, lane));
+    return imin(i, row_partner_i<2>(i, lane));
 }
 
 struct PanelCand {
@@ -100,29 +103,46 @@ struct PanelCand {
     int pad;
 };
 
+// FULL: nb == LU_NB (every panel but possibly the last), with no test per
+// column.  The column steps contain no branch apart from the candidate row's
+// publication and the barrier, so that the tail of one column's update
+// (columns j + 2 ..) can be scheduled into the latency of the next column's
+// reductions: rows that are not updated keep their values through selects,
+// and the pivots are kept in registers and stored at the end.
+template <bool FULL>
 __global__ void __launch_bounds__(LU_PANEL_THREADS)
     lu_panel(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb, int32_t *__restrict__ ipiv,
              int32_t *__restrict__ info)
 {
     constexpr int W = LU_PANEL_THREADS / 64;   // waves
-    // One barrier per column.  Before it, each wave publishes its best
-    // candidate and that candidate's whole row, and the owner of row j
-    // publishes row j; after it, every thread picks the pivot among the W
-    // candidates and reads the rows it needs.  The buffers alternate with the
+    // Rows never move between registers: each row held by a thread carries
+    // its current position in the panel (its label), and exchanging rows j
+    // and p exchanges two labels.  At the end every row is stored at the
+    // position its label names.  Ties between pivot candidates go to the
+    // smallest label: the first row of largest magnitude in the exchanged
+    // order.
+    //
+    // One barrier per column.  Before it, each wave publishes its candidate
+    // (largest magnitude, smallest position of that magnitude) and that
+    // candidate's whole row; after it, every wave reduces the W candidates
+    // the same way and reads the pivot row.  The buffers alternate with the
     // column's parity: a thread that reaches column j + 1's barrier has
     // finished every read of column j - 1's buffers.
     __shared__ PanelCand cand[2][W];
     __shared__ double crow[2][W][LU_NB];
-    __shared__ double rowj[2][LU_NB];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = (int)(n - k);   // rows of the panel (<= LU_ROWS * LU_PANEL_THREADS, checked on the host)
-    // thread 0 keeps the first zero pivot in a register (a global read per
-    // column would stall every column's barrier on memory latency)
-    int32_t zero_at = tid == 0 ? info[0] : 0;
+    if (FULL) nb = LU_NB;
+    // the first zero pivot, kept in registers (a global read per column
+    // would stall every column's barrier on memory latency)
+    int32_t zero_at = info[0];
+    int piv_at[LU_NB];   // the pivot position of each column
     double v[LU_ROWS][LU_NB];
+    int lab[LU_ROWS];   // the row's position; rows past the panel keep positions >= m
 #pragma unroll
     for (int r = 0; r < LU_ROWS; r++) {
         const int i = tid + LU_PANEL_THREADS * r;
+        lab[r] = i;
 #pragma unroll
         for (int c = 0; c < LU_NB; c++)
             v[r][c] = (i < m && c < nb) ? a[(k + i) * lda + k + c] : 0.0;
@@ -132,94 +152,97 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
     // constant and v stays in registers
     static_for<0, LU_NB>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
-        if (j < nb) {   // uniform
+        if (FULL || j < nb) {   // uniform
             constexpr int h = j & 1;
-            // ---- pivot candidates: the first row i >= j of largest |a[i][j]|,
-            // per thread, then per wave
-            double best = -1.0;
-            int bi = 0x7fffffff;
+            // ---- pivot candidates: per thread the largest |a[.][j]| among
+            // its rows at positions >= j and the smallest such position, then
+            // the same per wave
+            double x[LU_ROWS];
 #pragma unroll
-            for (int r = 0; r < LU_ROWS; r++) {
-                const int i = tid + LU_PANEL_THREADS * r;
-                if (i >= j && i < m) {
-                    const double x = fabs(v[r][j]);
-                    if (x > best) {
-                        best = x;
-                        bi = i;
-                    }
-                }
+            for (int r = 0; r < LU_ROWS; r++) x[r] = (lab[r] >= j && lab[r] < m) ? fabs(v[r][j]) : -1.0;
+            double mt = x[0];
+#pragma unroll
+            for (int r = 1; r < LU_ROWS; r++) mt = dmax(mt, x[r]);
+            int lt = 0x7fffffff, br = 0;
+#pragma unroll
+            for (int r = LU_ROWS - 1; r >= 0; r--) {
+                const bool t = x[r] == mt && lab[r] < lt;
+                lt = t ? lab[r] : lt;
+                br = t ? r : br;
             }
-            wave_best(best, bi, lane);
-            if (lane == 0) cand[h][wave] = PanelCand{best, bi, 0};
+            const double mw = wave_max(mt, lane);
+            const int pwv = wave_min(mt == mw ? lt : 0x7fffffff, lane);
+            if (lane == 0) cand[h][wave] = PanelCand{mw, pwv, 0};
+            if (lt == pwv) {   // the one lane of the wave that holds the candidate (positions are unique)
 #pragma unroll
-            for (int r = 0; r < LU_ROWS; r++) {
-                const int i = tid + LU_PANEL_THREADS * r;
-                if (i == bi) {
+                for (int r = 0; r < LU_ROWS; r++) {
+                    if (br == r) {
 #pragma unroll
-                    for (int c = 0; c < LU_NB; c++) crow[h][wave][c] = v[r][c];
-                }
-                if (i == j) {
-#pragma unroll
-                    for (int c = 0; c < LU_NB; c++) rowj[h][c] = v[r][c];
+                        for (int c = 0; c < LU_NB; c++) crow[h][wave][c] = v[r][c];
+                        asm volatile("" ::: "memory");   // keeps the four stores apart (merged, they index v at run time)
+                    }
                 }
             }
             __syncthreads();
-            // ---- the pivot: the best of the W wave candidates (the same
-            // sequence of comparisons in every thread)
-            double b = cand[h][0].best;
-            int p = cand[h][0].row, pw = 0;
-#pragma unroll
-            for (int w = 1; w < W; w++) {
-                const PanelCand cw = cand[h][w];
-                const bool t = beats(cw.best, cw.row, b, p);
-                b = t ? cw.best : b;
-                p = t ? cw.row : p;
-                pw = t ? w : pw;
-            }
-            if (tid == 0) {
-                ipiv[k + j] = (int32_t)(k + p);
-                if (b == 0.0 && zero_at == 0) zero_at = (int32_t)(k + j + 1);
-            }
+            // ---- the pivot: the same two reductions over the W wave
+            // candidates, lane l reading candidate l mod W
+            static_assert(W == 8, "the candidates are reduced within groups of 8 lanes");
+            const PanelCand cl = cand[h][lane & (W - 1)];
+            double b = cl.best;
+            b = dmax(b, dpp_d<0xB1>(b));
+            b = dmax(b, dpp_d<0x4E>(b));
+            b = dmax(b, dpp_d<0x141>(b));
+            int p = b == cl.best ? cl.row : 0x7fffffff;
+            p = imin(p, dpp_i<0xB1>(p));
+            p = imin(p, dpp_i<0x4E>(p));
+            p = imin(p, dpp_i<0x141>(p));
+            // every group of 8 lanes holds the result; the wave that published it
+            const int pw = __ffsll((long long)(__ballot(lane < W && cl.row == p) & 0xffull)) - 1;
+            piv_at[j] = p;
+            zero_at = (b == 0.0 && zero_at == 0) ? (int32_t)(k + j + 1) : zero_at;
             const double *rowp = crow[h][pw];
-            // ---- exchange rows j and p
+            double pr[LU_NB];   // the pivot row's columns j .. LU_NB - 1, read once
+#pragma unroll
+            for (int c = j; c < LU_NB; c++) pr[c] = rowp[c];
+            // ---- exchange positions j and p
+#pragma unroll
+            for (int r = 0; r < LU_ROWS; r++) lab[r] = lab[r] == j ? p : (lab[r] == p ? j : lab[r]);
+            // ---- scale the column below the pivot (a zero pivot scales
+            // nothing), update the panel's right part; the four quotients are
+            // independent, and column j + 1 comes first: the next pivot
+            // search waits for it alone
+            const double piv = pr[j];
+            bool up[LU_ROWS];
+            double l[LU_ROWS];
 #pragma unroll
             for (int r = 0; r < LU_ROWS; r++) {
-                const int i = tid + LU_PANEL_THREADS * r;
-                if (i == j) {
-#pragma unroll
-                    for (int c = 0; c < LU_NB; c++) v[r][c] = rowp[c];
-                } else if (i == p) {
-#pragma unroll
-                    for (int c = 0; c < LU_NB; c++) v[r][c] = rowj[h][c];
-                }
+                up[r] = lab[r] > j && lab[r] < m && piv != 0.0;
+                const double q = v[r][j] / piv;
+                l[r] = q;
+                v[r][j] = up[r] ? q : v[r][j];
             }
-            // ---- scale the column below the pivot, update the panel's right part
-            const double piv = rowp[j];
-            if (piv != 0.0) {
 #pragma unroll
-                for (int r = 0; r < LU_ROWS; r++) {
-                    const int i = tid + LU_PANEL_THREADS * r;
-                    if (i > j && i < m) {
-                        const double l = v[r][j] / piv;
-                        v[r][j] = l;
+            for (int c = j + 1; c < LU_NB; c++) {
 #pragma unroll
-                        for (int c = j + 1; c < LU_NB; c++) v[r][c] -= l * rowp[c];
-                    }
-                }
+                for (int r = 0; r < LU_ROWS; r++) v[r][c] = up[r] ? v[r][c] - l[r] * pr[c] : v[r][c];
             }
         }
     });
 
 #pragma unroll
     for (int r = 0; r < LU_ROWS; r++) {
-        const int i = tid + LU_PANEL_THREADS * r;
-        if (i < m) {
+        if (lab[r] < m) {
 #pragma unroll
             for (int c = 0; c < LU_NB; c++)
-                if (c < nb) a[(k + i) * lda + k + c] = v[r][c];
+                if (c < nb) a[(k + lab[r]) * lda + k + c] = v[r][c];
         }
     }
-    if (tid == 0) info[0] = zero_at;
+    if (tid == 0) {
+#pragma unroll
+        for (int j = 0; j < LU_NB; j++)
+            if (j < nb) ipiv[k + j] = (int32_t)(k + piv_at[j]);
+        info[0] = zero_at;
+    }
 }
 
 // The panel's swaps (rows k+j <-> ipiv[k+j], j = 0..nb-1 in order) on every
@@ -239,56 +262,62 @@ __device__ __forceinline__ int64_t lane_i64(int64_t x, int l)
 __global__ void __launch_bounds__(LU_SWAP_THREADS)
     lu_swap_trsm(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb, const int32_t *__restrict__ ipiv)
 {
+    // The kernel is a chain of latencies (the pivots, the permutation, the
+    // rows, the solve), so every step keeps its loads in flight together:
+    // the pivots and L11 are requested at once, and the row addresses are
+    // scalars read from the lanes that composed the permutation, with no LDS
+    // round trip between them.
+    static_assert(LU_SWAP_THREADS == 64 && 2 * LU_NB <= 64, "one wave composes the permutation");
+    static_assert((LU_NB * LU_NB) % LU_SWAP_THREADS == 0, "L11 is loaded in whole rounds");
+    constexpr int LR = LU_NB * LU_NB / LU_SWAP_THREADS;
     __shared__ double L[LU_NB][LU_NB + 1];
-    __shared__ int64_t dst[2 * LU_NB], src[2 * LU_NB];
-    __shared__ int npair;
-    for (int idx = threadIdx.x; idx < LU_NB * LU_NB; idx += LU_SWAP_THREADS) {
-        const int i = idx / LU_NB, j = idx % LU_NB;
-        L[i][j] = (i < nb && j < nb) ? a[(k + i) * lda + k + j] : 0.0;
+    const int lane = threadIdx.x;
+    const int32_t pv32 = ipiv[k + (lane < nb ? lane : 0)];   // unconditional: no wait at a branch join
+    double lv[LR];
+#pragma unroll
+    for (int t = 0; t < LR; t++) {
+        const int idx = lane + LU_SWAP_THREADS * t, i = idx / LU_NB, j = idx % LU_NB;
+        const int ic = i < nb ? i : 0, jc = j < nb ? j : 0;   // in bounds also for a short last panel
+        lv[t] = a[(k + ic) * lda + k + jc];
     }
-    {
-        // The workgroup is one wave.  Lane q holds touched row dst[q] and the
-        // original row src[q] whose content it holds after the swaps so far:
-        // rows k .. k+nb-1 in lanes 0 .. nb-1, pivot rows below the block
-        // appended as they first appear.
-        static_assert(LU_SWAP_THREADS == 64 && 2 * LU_NB <= 64, "one wave composes the permutation");
-        const int lane = threadIdx.x;
-        const int64_t pv = lane < nb ? (int64_t)ipiv[k + lane] : 0;
-        int64_t d = lane < nb ? k + lane : -1;
-        int64_t sr = d;
-        int cnt = nb;
-        // j and q are uniform, so every exchange is a scalar read of one lane
-        for (int j = 0; j < nb; j++) {
-            const int64_t pr = lane_i64(pv, j);
-            int q;
-            if (pr - k < nb) {
-                q = (int)(pr - k);   // inside the block (pivot rows are >= k + j)
+    // Lane q holds touched row d and the original row sr whose content it
+    // holds after the swaps so far: rows k .. k+nb-1 in lanes 0 .. nb-1,
+    // pivot rows below the block appended as they first appear.  j and q are
+    // uniform, so every exchange is a scalar read of one lane.
+    const int64_t pv = lane < nb ? (int64_t)pv32 : 0;
+    int64_t d = lane < nb ? k + lane : -1;
+    int64_t sr = d;
+    int cnt = nb;
+    for (int j = 0; j < nb; j++) {
+        const int64_t pr = lane_i64(pv, j);
+        int q;
+        if (pr - k < nb) {
+            q = (int)(pr - k);   // inside the block (pivot rows are >= k + j)
+        } else {
+            const unsigned long long hit = __ballot(lane >= nb && lane < cnt && d == pr);
+            if (hit) {
+                q = __ffsll((long long)hit) - 1;
             } else {
-                const unsigned long long hit = __ballot(lane >= nb && lane < cnt && d == pr);
-                if (hit) {
-                    q = __ffsll((long long)hit) - 1;
-                } else {
-                    q = cnt++;
-                    if (lane == q) d = sr = pr;
-                }
+                q = cnt++;
+                if (lane == q) d = sr = pr;
             }
-            const int64_t sj = lane_i64(sr, j), sq = lane_i64(sr, q);
-            if (lane == j) sr = sq;
-            if (lane == q) sr = sj;
         }
-        if (lane < cnt) {
-            dst[lane] = d;
-            src[lane] = sr;
-        }
-        if (lane == 0) npair = cnt;
+        const int64_t sj = lane_i64(sr, j), sq = lane_i64(sr, q);
+        if (lane == j) sr = sq;
+        if (lane == q) sr = sj;
+    }
+#pragma unroll
+    for (int t = 0; t < LR; t++) {
+        const int idx = lane + LU_SWAP_THREADS * t, i = idx / LU_NB, j = idx % LU_NB;
+        L[i][j] = (i < nb && j < nb) ? lv[t] : 0.0;
     }
     __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * LU_SWAP_THREADS + threadIdx.x;
-    if (c >= n || (c >= k && c < k + nb)) return;
-    const int np = npair;
+    const int64_t c = (int64_t)blockIdx.x * LU_SWAP_THREADS + lane;
+    const bool live = c < n && !(c >= k && c < k + nb);   // the panel's own columns are done
+    const int64_t cc = live ? c : (k + nb < n ? k + nb : 0);   // a column every lane may read
     double val[2 * LU_NB];
 #pragma unroll
-    for (int q = 0; q < 2 * LU_NB; q++) val[q] = q < np ? a[src[q] * lda + c] : 0.0;
+    for (int q = 0; q < 2 * LU_NB; q++) val[q] = q < cnt ? a[lane_i64(sr, q) * lda + cc] : 0.0;
     const bool right = c >= k + nb;
     if (right) {
         static_for<1, LU_NB>([&](auto ic) {
@@ -297,9 +326,15 @@ __global__ void __launch_bounds__(LU_SWAP_THREADS)
             for (int j = 0; j < i; j++) val[i] -= L[i][j] * val[j];
         });
     }
+    if (live) {
 #pragma unroll
-    for (int q = 0; q < 2 * LU_NB; q++)
-        if (q < np && (dst[q] != src[q] || (right && q < nb))) a[dst[q] * lda + c] = val[q];
+        for (int q = 0; q < 2 * LU_NB; q++) {
+            if (q < cnt) {
+                const int64_t dq = lane_i64(d, q), sq = lane_i64(sr, q);
+                if (dq != sq || (right && q < nb)) a[dq * lda + c] = val[q];
+            }
+        }
+    }
 }
 
 // A22 -= L21 U12 on 64 x 64 tiles: rows and columns >= k + nb.
@@ -438,7 +473,10 @@ hipError_t launch_lu(double *a, int64_t n, int64_t lda, int32_t *ipiv, int32_t *
     hipError_t e = hipGetLastError();
     for (int64_t k = 0; e == hipSuccess && k < n; k += LU_NB) {
         const int nb = (int)(n - k < LU_NB ? n - k : LU_NB);
-        hipLaunchKernelGGL(lu_panel, dim3(1), dim3(LU_PANEL_THREADS), 0, st, a, n, lda, k, nb, ipiv, info);
+        if (nb == LU_NB)
+            hipLaunchKernelGGL(lu_panel<true>, dim3(1), dim3(LU_PANEL_THREADS), 0, st, a, n, lda, k, nb, ipiv, info);
+        else
+            hipLaunchKernelGGL(lu_panel<false>, dim3(1), dim3(LU_PANEL_THREADS), 0, st, a, n, lda, k, nb, ipiv, info);
         if (n > nb)
             hipLaunchKernelGGL(lu_swap_trsm, dim3((unsigned)((n + LU_SWAP_THREADS - 1) / LU_SWAP_THREADS)),
                                dim3(LU_SWAP_THREADS), 0, st, a, n, lda, k, nb, ipiv);
