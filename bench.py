@@ -644,6 +644,8 @@ def main() -> int:
     ap.add_argument("--lu-only", action="store_true", help="only run the LU section (for kernel traces)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the batched-form section (for kernel traces)")
+    ap.add_argument("--paper2d-only", action="store_true",
+                    help="only run the 2048 x 2048 transform section (for kernel traces)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain 512 MiB copy (counter calibration)")
     args = ap.parse_args()
@@ -669,6 +671,9 @@ def main() -> int:
         return 0
     if args.lu_only:
         print(json.dumps({"lu_2048": lu_section(torch, fb)}), flush=True)
+        return 0
+    if args.paper2d_only:
+        print(json.dumps({"paper_2d_2048": paper_2d_section(torch, fb)}), flush=True)
         return 0
     if args.batched_only:
         print(json.dumps({"batched": batched_section(torch, fb)}), flush=True)

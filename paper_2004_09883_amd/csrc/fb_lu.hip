@@ -103,50 +103,50 @@ struct PanelCand {
     int pad;
 };
 
+// The factorization of one panel (columns k .. k+nb-1, rows k .. k+m-1)
+// from registers: thread t holds rows in v[r][0 .. nb), each with its
+// position in the panel in lab[r] (rows that are not in the panel carry a
+// position >= m).  Rows never move between registers: exchanging rows j and
+// p exchanges two positions, and at the end every row is stored at the
+// position it carries.  Ties between pivot candidates go to the smallest
+// position: the first row of largest magnitude in the exchanged order.
+//
+// One barrier per column.  Before it, each wave publishes its candidate
+// (largest magnitude, smallest position of that magnitude) and that
+// candidate's whole row; after it, every wave reduces the W candidates the
+// same way and reads the pivot row.  The buffers alternate with the
+// column's parity: a thread that reaches column j + 1's barrier has finished
+// every read of column j - 1's buffers.
+//
+// R: the register slots that can hold rows of the panel (slot r holds
+// physical rows t + LU_PANEL_THREADS r, so a panel of m rows needs
+// ceil(m / LU_PANEL_THREADS) of them); the others are not compiled in, which
+// shortens every column step of the short panels.
+//
 // FULL: nb == LU_NB (every panel but possibly the last), with no test per
 // column.  The column steps contain no branch apart from the candidate row's
 // publication and the barrier, so that the tail of one column's update
 // (columns j + 2 ..) can be scheduled into the latency of the next column's
 // reductions: rows that are not updated keep their values through selects,
 // and the pivots are kept in registers and stored at the end.
-template <bool FULL>
-__global__ void __launch_bounds__(LU_PANEL_THREADS)
-    lu_panel(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb, int32_t *__restrict__ ipiv,
-             int32_t *__restrict__ info)
+constexpr int LU_W = LU_PANEL_THREADS / 64;   // waves of the panel's workgroup
+struct PanelShared {
+    PanelCand cand[2][LU_W];
+    double crow[2][LU_W][LU_NB];
+};
+
+template <bool FULL, int R>
+__device__ __forceinline__ void panel_columns(double (&v)[LU_ROWS][LU_NB], int (&lab)[LU_ROWS],
+                                              double *__restrict__ a, int64_t lda, int64_t k, int m, int nb,
+                                              int32_t *__restrict__ ipiv, int32_t *__restrict__ info, PanelShared &sh)
 {
-    constexpr int W = LU_PANEL_THREADS / 64;   // waves
-    // Rows never move between registers: each row held by a thread carries
-    // its current position in the panel (its label), and exchanging rows j
-    // and p exchanges two labels.  At the end every row is stored at the
-    // position its label names.  Ties between pivot candidates go to the
-    // smallest label: the first row of largest magnitude in the exchanged
-    // order.
-    //
-    // One barrier per column.  Before it, each wave publishes its candidate
-    // (largest magnitude, smallest position of that magnitude) and that
-    // candidate's whole row; after it, every wave reduces the W candidates
-    // the same way and reads the pivot row.  The buffers alternate with the
-    // column's parity: a thread that reaches column j + 1's barrier has
-    // finished every read of column j - 1's buffers.
-    __shared__ PanelCand cand[2][W];
-    __shared__ double crow[2][W][LU_NB];
+    constexpr int W = LU_W;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m = (int)(n - k);   // rows of the panel (<= LU_ROWS * LU_PANEL_THREADS, checked on the host)
     if (FULL) nb = LU_NB;
     // the first zero pivot, kept in registers (a global read per column
     // would stall every column's barrier on memory latency)
     int32_t zero_at = info[0];
     int piv_at[LU_NB];   // the pivot position of each column
-    double v[LU_ROWS][LU_NB];
-    int lab[LU_ROWS];   // the row's position; rows past the panel keep positions >= m
-#pragma unroll
-    for (int r = 0; r < LU_ROWS; r++) {
-        const int i = tid + LU_PANEL_THREADS * r;
-        lab[r] = i;
-#pragma unroll
-        for (int c = 0; c < LU_NB; c++)
-            v[r][c] = (i < m && c < nb) ? a[(k + i) * lda + k + c] : 0.0;
-    }
 
     // columns as a compile-time sequence, so that every index into v is a
     // constant and v stays in registers
@@ -159,26 +159,26 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
             // the same per wave
             double x[LU_ROWS];
 #pragma unroll
-            for (int r = 0; r < LU_ROWS; r++) x[r] = (lab[r] >= j && lab[r] < m) ? fabs(v[r][j]) : -1.0;
+            for (int r = 0; r < R; r++) x[r] = (lab[r] >= j && lab[r] < m) ? fabs(v[r][j]) : -1.0;
             double mt = x[0];
 #pragma unroll
-            for (int r = 1; r < LU_ROWS; r++) mt = dmax(mt, x[r]);
+            for (int r = 1; r < R; r++) mt = dmax(mt, x[r]);
             int lt = 0x7fffffff, br = 0;
 #pragma unroll
-            for (int r = LU_ROWS - 1; r >= 0; r--) {
+            for (int r = R - 1; r >= 0; r--) {
                 const bool t = x[r] == mt && lab[r] < lt;
                 lt = t ? lab[r] : lt;
                 br = t ? r : br;
             }
             const double mw = wave_max(mt, lane);
             const int pwv = wave_min(mt == mw ? lt : 0x7fffffff, lane);
-            if (lane == 0) cand[h][wave] = PanelCand{mw, pwv, 0};
+            if (lane == 0) sh.cand[h][wave] = PanelCand{mw, pwv, 0};
             if (lt == pwv) {   // the one lane of the wave that holds the candidate (positions are unique)
 #pragma unroll
-                for (int r = 0; r < LU_ROWS; r++) {
+                for (int r = 0; r < R; r++) {
                     if (br == r) {
 #pragma unroll
-                        for (int c = 0; c < LU_NB; c++) crow[h][wave][c] = v[r][c];
+                        for (int c = 0; c < LU_NB; c++) sh.crow[h][wave][c] = v[r][c];
                         asm volatile("" ::: "memory");   // keeps the four stores apart (merged, they index v at run time)
                     }
                 }
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
             // ---- the pivot: the same two reductions over the W wave
             // candidates, lane l reading candidate l mod W
             static_assert(W == 8, "the candidates are reduced within groups of 8 lanes");
-            const PanelCand cl = cand[h][lane & (W - 1)];
+            const PanelCand cl = sh.cand[h][lane & (W - 1)];
             double b = cl.best;
             b = dmax(b, dpp_d<0xB1>(b));
             b = dmax(b, dpp_d<0x4E>(b));
@@ -200,13 +200,13 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
             const int pw = __ffsll((long long)(__ballot(lane < W && cl.row == p) & 0xffull)) - 1;
             piv_at[j] = p;
             zero_at = (b == 0.0 && zero_at == 0) ? (int32_t)(k + j + 1) : zero_at;
-            const double *rowp = crow[h][pw];
+            const double *rowp = sh.crow[h][pw];
             double pr[LU_NB];   // the pivot row's columns j .. LU_NB - 1, read once
 #pragma unroll
             for (int c = j; c < LU_NB; c++) pr[c] = rowp[c];
             // ---- exchange positions j and p
 #pragma unroll
-            for (int r = 0; r < LU_ROWS; r++) lab[r] = lab[r] == j ? p : (lab[r] == p ? j : lab[r]);
+            for (int r = 0; r < R; r++) lab[r] = lab[r] == j ? p : (lab[r] == p ? j : lab[r]);
             // ---- scale the column below the pivot (a zero pivot scales
             // nothing), update the panel's right part; the four quotients are
             // independent, and column j + 1 comes first: the next pivot
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
             bool up[LU_ROWS];
             double l[LU_ROWS];
 #pragma unroll
-            for (int r = 0; r < LU_ROWS; r++) {
+            for (int r = 0; r < R; r++) {
                 up[r] = lab[r] > j && lab[r] < m && piv != 0.0;
                 const double q = v[r][j] / piv;
                 l[r] = q;
@@ -224,13 +224,13 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
 #pragma unroll
             for (int c = j + 1; c < LU_NB; c++) {
 #pragma unroll
-                for (int r = 0; r < LU_ROWS; r++) v[r][c] = up[r] ? v[r][c] - l[r] * pr[c] : v[r][c];
+                for (int r = 0; r < R; r++) v[r][c] = up[r] ? v[r][c] - l[r] * pr[c] : v[r][c];
             }
         }
     });
 
 #pragma unroll
-    for (int r = 0; r < LU_ROWS; r++) {
+    for (int r = 0; r < R; r++) {
         if (lab[r] < m) {
 #pragma unroll
             for (int c = 0; c < LU_NB; c++)
@@ -243,6 +243,30 @@ __global__ void __launch_bounds__(LU_PANEL_THREADS)
             if (j < nb) ipiv[k + j] = (int32_t)(k + piv_at[j]);
         info[0] = zero_at;
     }
+}
+
+// The first panel (and, with the lookahead off, every panel): rows k ..
+// n-1 of columns k .. k+nb-1 loaded into registers, then factored.
+template <bool FULL, int R>
+__global__ void __launch_bounds__(LU_PANEL_THREADS)
+    lu_panel(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb, int32_t *__restrict__ ipiv,
+             int32_t *__restrict__ info)
+{
+    __shared__ PanelShared sh;
+    const int tid = threadIdx.x;
+    const int m = (int)(n - k);   // rows of the panel (<= LU_ROWS * LU_PANEL_THREADS, checked on the host)
+    if (FULL) nb = LU_NB;
+    double v[LU_ROWS][LU_NB];
+    int lab[LU_ROWS];   // the row's position; rows past the panel keep positions >= m
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int i = tid + LU_PANEL_THREADS * r;
+        lab[r] = i;
+#pragma unroll
+        for (int c = 0; c < LU_NB; c++)
+            v[r][c] = (i < m && c < nb) ? a[(k + i) * lda + k + c] : 0.0;
+    }
+    panel_columns<FULL, R>(v, lab, a, lda, k, m, nb, ipiv, info, sh);
 }
 
 // The panel's swaps (rows k+j <-> ipiv[k+j], j = 0..nb-1 in order) on every
@@ -259,6 +283,38 @@ __device__ __forceinline__ int64_t lane_i64(int64_t x, int l)
     const unsigned hi = __builtin_amdgcn_readlane((unsigned)((uint64_t)x >> 32), l);
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
+// The panel's swaps composed by one wave into one permutation of the rows
+// they touch: lane q < the returned count holds touched row d and the
+// original row sr whose content moves there.  pv is ipiv[k + lane] for lanes
+// < nb.  Lanes 0 .. nb-1 start with rows k .. k+nb-1; pivot rows below the
+// block are appended as they first appear.  j and q are uniform, so every
+// exchange is a scalar read of one lane.
+__device__ __forceinline__ int compose_perm(int64_t pv, int64_t k, int nb, int lane, int64_t &d, int64_t &sr)
+{
+    d = lane < nb ? k + lane : -1;
+    sr = d;
+    int cnt = nb;
+    for (int j = 0; j < nb; j++) {
+        const int64_t pr = lane_i64(pv, j);
+        int q;
+        if (pr - k < nb) {
+            q = (int)(pr - k);   // inside the block (pivot rows are >= k + j)
+        } else {
+            const unsigned long long hit = __ballot(lane >= nb && lane < cnt && d == pr);
+            if (hit) {
+                q = __ffsll((long long)hit) - 1;
+            } else {
+                q = cnt++;
+                if (lane == q) d = sr = pr;
+            }
+        }
+        const int64_t sj = lane_i64(sr, j), sq = lane_i64(sr, q);
+        if (lane == j) sr = sq;
+        if (lane == q) sr = sj;
+    }
+    return cnt;
+}
+
 __global__ void __launch_bounds__(LU_SWAP_THREADS)
     lu_swap_trsm(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb, const int32_t *__restrict__ ipiv)
 {
@@ -280,32 +336,9 @@ __global__ void __launch_bounds__(LU_SWAP_THREADS)
         const int ic = i < nb ? i : 0, jc = j < nb ? j : 0;   // in bounds also for a short last panel
         lv[t] = a[(k + ic) * lda + k + jc];
     }
-    // Lane q holds touched row d and the original row sr whose content it
-    // holds after the swaps so far: rows k .. k+nb-1 in lanes 0 .. nb-1,
-    // pivot rows below the block appended as they first appear.  j and q are
-    // uniform, so every exchange is a scalar read of one lane.
     const int64_t pv = lane < nb ? (int64_t)pv32 : 0;
-    int64_t d = lane < nb ? k + lane : -1;
-    int64_t sr = d;
-    int cnt = nb;
-    for (int j = 0; j < nb; j++) {
-        const int64_t pr = lane_i64(pv, j);
-        int q;
-        if (pr - k < nb) {
-            q = (int)(pr - k);   // inside the block (pivot rows are >= k + j)
-        } else {
-            const unsigned long long hit = __ballot(lane >= nb && lane < cnt && d == pr);
-            if (hit) {
-                q = __ffsll((long long)hit) - 1;
-            } else {
-                q = cnt++;
-                if (lane == q) d = sr = pr;
-            }
-        }
-        const int64_t sj = lane_i64(sr, j), sq = lane_i64(sr, q);
-        if (lane == j) sr = sq;
-        if (lane == q) sr = sj;
-    }
+    int64_t d, sr;
+    const int cnt = compose_perm(pv, k, nb, lane, d, sr);
 #pragma unroll
     for (int t = 0; t < LR; t++) {
         const int idx = lane + LU_SWAP_THREADS * t, i = idx / LU_NB, j = idx % LU_NB;
@@ -467,16 +500,312 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// ---- one launch per panel: the previous panel's update and the next panel
+//
+// lu_step(k) runs after panel k (columns k .. k+nb-1) has been factored.  Its
+// workgroups split the work by columns, each owning its columns in every
+// row, so that the row exchanges can be applied in place with no other
+// workgroup reading or writing those rows' elements:
+//   workgroup 0     the next panel's columns s .. s+nb2-1 (s = k + nb): the
+//                   exchanges, U12 = L11^-1 A12, A22 -= L21 U12, then the
+//                   factorization of panel s from its registers (the
+//                   lookahead: the next panel starts as soon as its own
+//                   columns are up to date);
+//   the next ones   the same update on 16-column strips right of it;
+//   the last ones   the exchanges alone on the columns left of the panel,
+//                   one column per thread.
+// Every element receives the same operations in the same order as in
+// lu_swap_trsm and lu_gemm, so the factors are bitwise those of the
+// three-kernel schedule.
+struct StripShared {
+    double L[LU_NB][LU_NB + 1];          // L11
+    double U[LU_NB][LU_NB + 1];          // the strip's U12 block
+    double slot[2 * LU_NB][LU_NB];       // the touched rows' contents, by composed index
+    int64_t dst[2 * LU_NB], src[2 * LU_NB];
+    int np;
+    int16_t send[LU_MAX_N], recv[LU_MAX_N];   // per row from k: the slot it sends / receives, or -1
+};
+
+// Columns [c0, c0 + w) of rows k .. n-1 after panel k: thread t holds rows
+// k + t + LU_PANEL_THREADS r in v[r][0 .. w).  keep: store only the U12 rows
+// and leave the rows below them, updated, in v.
+template <int R>
+__device__ __forceinline__ void strip_update(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb,
+                                             const int32_t *__restrict__ ipiv, int64_t c0, int w, bool keep,
+                                             double (&v)[LU_ROWS][LU_NB], StripShared &sh)
+{
+    static_assert(2 * LU_NB <= 64, "one wave composes the permutation");
+    static_assert(LU_NB * LU_NB <= LU_PANEL_THREADS, "one L11 element per thread");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = (int)(n - k);
+    // ---- every load that does not depend on the permutation goes first:
+    // the strip's rows, L11 and the first half of L21 (four panel columns
+    // per quarter, two quarters in flight)
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int i = tid + LU_PANEL_THREADS * r;
+#pragma unroll
+        for (int c = 0; c < LU_NB; c++) v[r][c] = (i < m && c < w) ? a[(k + i) * lda + c0 + c] : 0.0;
+    }
+    const int li = (tid / LU_NB) % LU_NB, lj = tid % LU_NB;
+    const double lv = a[(k + (li < nb ? li : 0)) * lda + k + (lj < nb ? lj : 0)];   // clamped: every thread loads
+    const int32_t pv32 = ipiv[k + (lane < nb ? lane : 0)];
+    double lq[2][LU_ROWS][4];
+    auto load_quarter = [&](auto qc, double (&dq)[LU_ROWS][4]) {
+        constexpr int q = decltype(qc)::value;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int i = tid + LU_PANEL_THREADS * r;
+#pragma unroll
+            for (int t = 0; t < 4; t++)
+                dq[r][t] = (i >= nb && i < m && 4 * q + t < nb) ? a[(k + i) * lda + k + 4 * q + t] : 0.0;
+        }
+    };
+    load_quarter(std::integral_constant<int, 0>{}, lq[0]);
+    load_quarter(std::integral_constant<int, 1>{}, lq[1]);
+    // ---- the permutation, composed by wave 0, as maps over the rows
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int i = tid + LU_PANEL_THREADS * r;
+        if (i < m) {
+            sh.send[i] = -1;
+            sh.recv[i] = -1;
+        }
+    }
+    if (tid < LU_NB * LU_NB) sh.L[li][lj] = (li < nb && lj < nb) ? lv : 0.0;
+    int64_t d = -1, sr = -1;
+    int cnt = 0;
+    if (wave == 0) cnt = compose_perm(lane < nb ? (int64_t)pv32 : 0, k, nb, lane, d, sr);
+    __syncthreads();
+    if (wave == 0 && lane < cnt) {
+        sh.send[sr - k] = (int16_t)lane;
+        sh.recv[d - k] = (int16_t)lane;
+    }
+    __syncthreads();
+    // ---- the exchanges: the holders of the source rows publish them, the
+    // holders of the destination rows take them
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int i = tid + LU_PANEL_THREADS * r;
+        const int q = i < m ? sh.send[i] : -1;
+        if (q >= 0) {
+#pragma unroll
+            for (int c = 0; c < LU_NB; c++) sh.slot[q][c] = v[r][c];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int i = tid + LU_PANEL_THREADS * r;
+        const int q = i < m ? sh.recv[i] : -1;
+        if (q >= 0) {
+#pragma unroll
+            for (int c = 0; c < LU_NB; c++) v[r][c] = sh.slot[q][c];
+        }
+    }
+    // ---- U12 = L11^-1 A12: rows k .. k+nb-1 are rows r = 0 of threads
+    // 0 .. nb-1; one thread per column solves in registers
+    if (tid < LU_NB) {
+#pragma unroll
+        for (int c = 0; c < LU_NB; c++) sh.U[tid][c] = tid < nb ? v[0][c] : 0.0;
+    }
+    __syncthreads();
+    if (tid < w) {
+        double col[LU_NB];
+#pragma unroll
+        for (int i = 0; i < LU_NB; i++) col[i] = sh.U[i][tid];
+        static_for<1, LU_NB>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+#pragma unroll
+            for (int j = 0; j < i; j++) col[i] -= sh.L[i][j] * col[j];
+        });
+#pragma unroll
+        for (int i = 0; i < LU_NB; i++) sh.U[i][tid] = col[i];
+    }
+    __syncthreads();
+    // ---- A22 -= L21 U12, the panel's columns in order (on every row held:
+    // the U12 rows are restored afterwards, rows past the end are never
+    // stored)
+    static_for<0, 4>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        static_for<0, 4>([&](auto tc) {
+            constexpr int t = decltype(tc)::value, j = 4 * q + t;
+            if (j < nb) {   // uniform
+                double u[LU_NB];
+#pragma unroll
+                for (int c = 0; c < LU_NB; c++) u[c] = sh.U[j][c];
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+#pragma unroll
+                    for (int c = 0; c < LU_NB; c++) v[r][c] -= lq[q & 1][r][t] * u[c];
+                }
+            }
+        });
+        if constexpr (q + 2 < 4) load_quarter(std::integral_constant<int, q + 2>{}, lq[q & 1]);
+    });
+    if (tid < nb) {
+#pragma unroll
+        for (int c = 0; c < LU_NB; c++) v[0][c] = sh.U[tid][c];
+    }
+    // ---- store
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int i = tid + LU_PANEL_THREADS * r;
+        if (i < m && (!keep || i < nb)) {
+#pragma unroll
+            for (int c = 0; c < LU_NB; c++)
+                if (c < w) a[(k + i) * lda + c0 + c] = v[r][c];
+        }
+    }
+}
+
+// The exchanges alone on columns [c0, min(c0 + LU_PANEL_THREADS, k)), one
+// column per thread.
+__device__ __forceinline__ void left_swaps(double *__restrict__ a, int64_t lda, int64_t k, int nb,
+                                           const int32_t *__restrict__ ipiv, int64_t c0, StripShared &sh)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (wave == 0) {
+        const int32_t pv32 = ipiv[k + (lane < nb ? lane : 0)];
+        int64_t d, sr;
+        const int cnt = compose_perm(lane < nb ? (int64_t)pv32 : 0, k, nb, lane, d, sr);
+        if (lane < cnt) {
+            sh.dst[lane] = d;
+            sh.src[lane] = sr;
+        }
+        if (lane == 0) sh.np = cnt;
+    }
+    __syncthreads();
+    const int64_t c = c0 + tid;
+    if (c >= k) return;
+    const int np = sh.np;
+    double val[2 * LU_NB];
+#pragma unroll
+    for (int q = 0; q < 2 * LU_NB; q++) val[q] = q < np ? a[sh.src[q] * lda + c] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 2 * LU_NB; q++)
+        if (q < np && sh.dst[q] != sh.src[q]) a[sh.dst[q] * lda + c] = val[q];
+}
+
+#ifndef FB_LU_STRIP_DELAY
+#define FB_LU_STRIP_DELAY 0   // pauses of 127 x 64 cycles per register slot before the strips start
+#endif
+
+// grid: nfirst (0 or 1: the next panel's workgroup), nstrips, then the
+// left-column workgroups.  FULL_NEXT: the next panel is LU_NB wide.  R: the
+// register slots that rows k .. n-1 need.
+template <bool FULL_NEXT, int R>
+__global__ void __launch_bounds__(LU_PANEL_THREADS)
+    lu_step(double *__restrict__ a, int64_t n, int64_t lda, int64_t k, int nb, int32_t *__restrict__ ipiv,
+            int32_t *__restrict__ info, int nfirst, int nstrips)
+{
+    __shared__ StripShared ss;
+    __shared__ PanelShared ps;
+    const int b = blockIdx.x;
+    const int64_t s = k + nb;   // the first column right of panel k
+    const int nb2 = (int)(n - s < LU_NB ? n - s : LU_NB);   // the next panel's width (when s < n)
+    if (b < nfirst) {
+        double v[LU_ROWS][LU_NB];
+        strip_update<R>(a, n, lda, k, nb, ipiv, s, nb2, true, v, ss);
+        // rows k + nb .. n-1 are the next panel's rows 0 .. n-s-1; the U12
+        // rows above them are done
+        const int m = (int)(n - k);
+        int lab[LU_ROWS];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int i = threadIdx.x + LU_PANEL_THREADS * r;
+            lab[r] = (i >= nb && i < m) ? i - nb : 0x3fffffff;
+        }
+        panel_columns<FULL_NEXT, R>(v, lab, a, lda, s, m - nb, nb2, ipiv, info, ps);
+    } else if (b < nfirst + nstrips) {
+        // the strips have the length of the next panel's factorization to
+        // finish; they start after a pause, so that workgroup 0's own loads
+        // do not queue behind theirs
+        for (int t = 0; nfirst && t < FB_LU_STRIP_DELAY * R; t++) __builtin_amdgcn_s_sleep(127);
+        const int64_t c0 = s + nb2 + (int64_t)LU_NB * (b - nfirst);
+        const int w = (int)(n - c0 < LU_NB ? n - c0 : LU_NB);
+        double v[LU_ROWS][LU_NB];
+        strip_update<R>(a, n, lda, k, nb, ipiv, c0, w, false, v, ss);
+    } else {
+        for (int t = 0; nfirst && t < FB_LU_STRIP_DELAY * R; t++) __builtin_amdgcn_s_sleep(127);
+        left_swaps(a, lda, k, nb, ipiv, (int64_t)LU_PANEL_THREADS * (b - nfirst - nstrips), ss);
+    }
+}
+
+#ifndef FB_LU_LOOKAHEAD
+#define FB_LU_LOOKAHEAD 1   // 0: three launches per panel (lu_panel, lu_swap_trsm, lu_gemm)
+#endif
+
+// R = ceil(m / LU_PANEL_THREADS) register slots for m rows
+template <int R> struct LuKernels {
+    static void panel(bool full, double *a, int64_t n, int64_t lda, int64_t k, int nb, int32_t *ipiv, int32_t *info,
+                      hipStream_t st)
+    {
+        if (full)
+            hipLaunchKernelGGL((lu_panel<true, R>), dim3(1), dim3(LU_PANEL_THREADS), 0, st, a, n, lda, k, nb, ipiv, info);
+        else
+            hipLaunchKernelGGL((lu_panel<false, R>), dim3(1), dim3(LU_PANEL_THREADS), 0, st, a, n, lda, k, nb, ipiv, info);
+    }
+    static void step(bool full_next, unsigned grid, double *a, int64_t n, int64_t lda, int64_t k, int nb,
+                     int32_t *ipiv, int32_t *info, int nfirst, int nstrips, hipStream_t st)
+    {
+        if (full_next)
+            hipLaunchKernelGGL((lu_step<true, R>), dim3(grid), dim3(LU_PANEL_THREADS), 0, st, a, n, lda, k, nb, ipiv,
+                               info, nfirst, nstrips);
+        else
+            hipLaunchKernelGGL((lu_step<false, R>), dim3(grid), dim3(LU_PANEL_THREADS), 0, st, a, n, lda, k, nb, ipiv,
+                               info, nfirst, nstrips);
+    }
+};
+static_assert(LU_ROWS == 4, "the launches below instantiate 1 .. 4 register slots");
+static void launch_panel(int64_t m, bool full, double *a, int64_t n, int64_t lda, int64_t k, int nb, int32_t *ipiv,
+                         int32_t *info, hipStream_t st)
+{
+    switch ((m + LU_PANEL_THREADS - 1) / LU_PANEL_THREADS) {
+    case 1: LuKernels<1>::panel(full, a, n, lda, k, nb, ipiv, info, st); break;
+    case 2: LuKernels<2>::panel(full, a, n, lda, k, nb, ipiv, info, st); break;
+    case 3: LuKernels<3>::panel(full, a, n, lda, k, nb, ipiv, info, st); break;
+    default: LuKernels<4>::panel(full, a, n, lda, k, nb, ipiv, info, st); break;
+    }
+}
+static void launch_step(int64_t m, bool full_next, unsigned grid, double *a, int64_t n, int64_t lda, int64_t k, int nb,
+                        int32_t *ipiv, int32_t *info, int nfirst, int nstrips, hipStream_t st)
+{
+    switch ((m + LU_PANEL_THREADS - 1) / LU_PANEL_THREADS) {
+    case 1: LuKernels<1>::step(full_next, grid, a, n, lda, k, nb, ipiv, info, nfirst, nstrips, st); break;
+    case 2: LuKernels<2>::step(full_next, grid, a, n, lda, k, nb, ipiv, info, nfirst, nstrips, st); break;
+    case 3: LuKernels<3>::step(full_next, grid, a, n, lda, k, nb, ipiv, info, nfirst, nstrips, st); break;
+    default: LuKernels<4>::step(full_next, grid, a, n, lda, k, nb, ipiv, info, nfirst, nstrips, st); break;
+    }
+}
+
 hipError_t launch_lu(double *a, int64_t n, int64_t lda, int32_t *ipiv, int32_t *info, hipStream_t st)
 {
     hipLaunchKernelGGL(lu_init, dim3(1), dim3(64), 0, st, info);
     hipError_t e = hipGetLastError();
+    if (FB_LU_LOOKAHEAD) {
+        const int nb0 = (int)(n < LU_NB ? n : LU_NB);
+        if (e == hipSuccess) {
+            launch_panel(n, nb0 == LU_NB, a, n, lda, 0, nb0, ipiv, info, st);
+            e = hipGetLastError();
+        }
+        for (int64_t k = 0; e == hipSuccess && k < n; k += LU_NB) {
+            const int nb = (int)(n - k < LU_NB ? n - k : LU_NB);
+            const int64_t s = k + nb;
+            const int nfirst = s < n ? 1 : 0;
+            const int64_t nb2 = s < n ? (n - s < LU_NB ? n - s : LU_NB) : 0;
+            const int nstrips = s < n ? (int)((n - s - nb2 + LU_NB - 1) / LU_NB) : 0;
+            const int nleft = (int)((k + LU_PANEL_THREADS - 1) / LU_PANEL_THREADS);
+            const unsigned grid = (unsigned)(nfirst + nstrips + nleft);
+            if (grid == 0) continue;
+            launch_step(n - k, nb2 == LU_NB || nfirst == 0, grid, a, n, lda, k, nb, ipiv, info, nfirst, nstrips, st);
+            e = hipGetLastError();
+        }
+        return e;
+    }
     for (int64_t k = 0; e == hipSuccess && k < n; k += LU_NB) {
         const int nb = (int)(n - k < LU_NB ? n - k : LU_NB);
-        if (nb == LU_NB)
-            hipLaunchKernelGGL(lu_panel<true>, dim3(1), dim3(LU_PANEL_THREADS), 0, st, a, n, lda, k, nb, ipiv, info);
-        else
-            hipLaunchKernelGGL(lu_panel<false>, dim3(1), dim3(LU_PANEL_THREADS), 0, st, a, n, lda, k, nb, ipiv, info);
+        launch_panel(n - k, nb == LU_NB, a, n, lda, k, nb, ipiv, info, st);
         if (n > nb)
             hipLaunchKernelGGL(lu_swap_trsm, dim3((unsigned)((n + LU_SWAP_THREADS - 1) / LU_SWAP_THREADS)),
                                dim3(LU_SWAP_THREADS), 0, st, a, n, lda, k, nb, ipiv);
