@@ -541,11 +541,25 @@ __device__ __forceinline__ void strip_update(double *__restrict__ a, int64_t n, 
     // ---- every load that does not depend on the permutation goes first:
     // the strip's rows, L11 and the first half of L21 (four panel columns
     // per quarter, two quarters in flight)
+    // Every load is unconditional (rows past the end read the last row
+    // again: they are never stored, published or used as candidates), so
+    // that each row's 128 bytes are read with 16-byte accesses and no load
+    // waits at a branch.  A strip is called with nb == LU_NB (a panel is
+    // followed by columns only when it is whole) and m > nb.
+    if (w == LU_NB) {
 #pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int i = tid + LU_PANEL_THREADS * r;
+        for (int r = 0; r < R; r++) {
+            const int i = tid + LU_PANEL_THREADS * r, ic = i < m ? i : m - 1;
 #pragma unroll
-        for (int c = 0; c < LU_NB; c++) v[r][c] = (i < m && c < w) ? a[(k + i) * lda + c0 + c] : 0.0;
+            for (int c = 0; c < LU_NB; c++) v[r][c] = a[(k + ic) * lda + c0 + c];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int i = tid + LU_PANEL_THREADS * r, ic = i < m ? i : m - 1;
+#pragma unroll
+            for (int c = 0; c < LU_NB; c++) v[r][c] = a[(k + ic) * lda + c0 + (c < w ? c : w - 1)];
+        }
     }
     const int li = (tid / LU_NB) % LU_NB, lj = tid % LU_NB;
     const double lv = a[(k + (li < nb ? li : 0)) * lda + k + (lj < nb ? lj : 0)];   // clamped: every thread loads
@@ -555,10 +569,9 @@ __device__ __forceinline__ void strip_update(double *__restrict__ a, int64_t n, 
         constexpr int q = decltype(qc)::value;
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            const int i = tid + LU_PANEL_THREADS * r;
+            const int i = tid + LU_PANEL_THREADS * r, ic = i < nb ? nb : (i < m ? i : m - 1);   // rows of L21
 #pragma unroll
-            for (int t = 0; t < 4; t++)
-                dq[r][t] = (i >= nb && i < m && 4 * q + t < nb) ? a[(k + i) * lda + k + 4 * q + t] : 0.0;
+            for (int t = 0; t < 4; t++) dq[r][t] = a[(k + ic) * lda + k + 4 * q + t];
         }
     };
     load_quarter(std::integral_constant<int, 0>{}, lq[0]);
@@ -624,8 +637,8 @@ __device__ __forceinline__ void strip_update(double *__restrict__ a, int64_t n, 
     }
     __syncthreads();
     // ---- A22 -= L21 U12, the panel's columns in order (on every row held:
-    // the U12 rows are restored afterwards, rows past the end are never
-    // stored)
+    // the U12 rows, which read some row of L21, are restored afterwards;
+    // rows past the end are never stored)
     static_for<0, 4>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         static_for<0, 4>([&](auto tc) {
@@ -652,9 +665,14 @@ __device__ __forceinline__ void strip_update(double *__restrict__ a, int64_t n, 
     for (int r = 0; r < R; r++) {
         const int i = tid + LU_PANEL_THREADS * r;
         if (i < m && (!keep || i < nb)) {
+            if (w == LU_NB) {
 #pragma unroll
-            for (int c = 0; c < LU_NB; c++)
-                if (c < w) a[(k + i) * lda + c0 + c] = v[r][c];
+                for (int c = 0; c < LU_NB; c++) a[(k + i) * lda + c0 + c] = v[r][c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < LU_NB; c++)
+                    if (c < w) a[(k + i) * lda + c0 + c] = v[r][c];
+            }
         }
     }
 }
