@@ -59,6 +59,21 @@ def test_lu_with_row_stride_keeps_padding():
     assert np.all(buf[:, n:] == 0.0)   # the padding columns are not touched
 
 
+@pytest.mark.parametrize("n,lda", [(1537, 1601), (2047, 2051)])
+def test_lu_large_with_row_stride(n, lda):
+    """Odd row strides at sizes where the rows need 3 and 4 register slots,
+    the trailing strips are ragged and the last panel is short: the rows
+    past the end and the padding columns are read but never written."""
+    print(f"lu n={n} lda={lda}", flush=True)
+    a = np.random.default_rng(n + lda).uniform(-1, 1, (n, n))
+    lu, ipiv, info, buf = gpu_lu(a, lda)
+    lu_ref, ipiv_ref, info_ref = oracle.lu(a)
+    assert info == info_ref == 0
+    assert np.array_equal(ipiv, ipiv_ref)
+    assert np.max(np.abs(lu - lu_ref)) <= 1e-11 * np.max(np.abs(lu_ref))
+    assert np.all(buf[:, n:] == 0.0)
+
+
 def test_lu_singular_and_special_matrices():
     a = np.arange(64.0 * 64).reshape(64, 64) % 7 - 3.0
     a[:, 20] = 0.0
