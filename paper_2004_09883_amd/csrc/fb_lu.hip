@@ -9,14 +9,22 @@
 //             workgroup holds the whole panel in registers, four rows per
 //             thread of 512, so n <= 2048, and exchanges rows by relabelling
 //             them;
-//   lu_swap_trsm  applies the panel's row swaps, in order, to every column
-//             outside the panel, then U12 = L11^-1 A12 for the columns right
-//             of it (one thread per column, L11 in LDS);
-//   lu_gemm_mfma  A22 -= L21 U12 on 64 x 64 tiles (L21 and U12 tiles in
-//             LDS) on the binary64 matrix cores (lu_gemm: the same on the
-//             vector units, FB_LU_MFMA = 0).
+//   the update of the other columns: the panel's row exchanges, in order,
+//             on every column outside the panel, U12 = L11^-1 A12 for the
+//             columns right of it, A22 -= L21 U12.
+// Two schedules of the same operations:
+//   FB_LU_LOOKAHEAD = 1 (default): lu_panel for the first panel, then one
+//             lu_step per panel k, whose workgroup 0 updates panel k+1's
+//             columns and factors panel k+1 while the other workgroups
+//             update the columns right of it (16-column strips) and apply
+//             the exchanges left of panel k;
+//   FB_LU_LOOKAHEAD = 0: three launches per panel, lu_panel, lu_swap_trsm
+//             (exchanges and U12, one thread per column) and lu_gemm_mfma
+//             (A22 on 64 x 64 tiles on the binary64 matrix cores; lu_gemm:
+//             the same on the vector units, FB_LU_MFMA = 0).
 // Every element receives its updates in increasing column order j, as in
-// unblocked elimination (both update kernels give the same bits).
+// unblocked elimination, so both schedules and both update kernels give
+// the same bits.
 #include <hip/hip_runtime.h>
 
 #include "fb_device.hpp"
