@@ -105,6 +105,27 @@ __device__ __forceinline__ int wave_min(int i, int lane)
     return imin(i, row_partner_i<2>(i, lane));
 }
 
+// step S (0 .. 5) of wave_max / wave_min, so that other work can be placed
+// between the steps
+template <int S> __device__ __forceinline__ double wave_max_step(double x, int lane)
+{
+    if constexpr (S == 0) return dmax(x, dpp_d<0xB1>(x));
+    else if constexpr (S == 1) return dmax(x, dpp_d<0x4E>(x));
+    else if constexpr (S == 2) return dmax(x, dpp_d<0x141>(x));
+    else if constexpr (S == 3) return dmax(x, dpp_d<0x140>(x));
+    else if constexpr (S == 4) return dmax(x, row_partner_d<1>(x, lane));
+    else return dmax(x, row_partner_d<2>(x, lane));
+}
+template <int S> __device__ __forceinline__ int wave_min_step(int i, int lane)
+{
+    if constexpr (S == 0) return imin(i, dpp_i<0xB1>(i));
+    else if constexpr (S == 1) return imin(i, dpp_i<0x4E>(i));
+    else if constexpr (S == 2) return imin(i, dpp_i<0x141>(i));
+    else if constexpr (S == 3) return imin(i, dpp_i<0x140>(i));
+    else if constexpr (S == 4) return imin(i, row_partner_i<1>(i, lane));
+    else return imin(i, row_partner_i<2>(i, lane));
+}
+
 struct PanelCand {
     double best;
     int row;
@@ -133,10 +154,13 @@ struct PanelCand {
 //
 // FULL: nb == LU_NB (every panel but possibly the last), with no test per
 // column.  The column steps contain no branch apart from the candidate row's
-// publication and the barrier, so that the tail of one column's update
-// (columns j + 2 ..) can be scheduled into the latency of the next column's
-// reductions: rows that are not updated keep their values through selects,
-// and the pivots are kept in registers and stored at the end.
+// publication and the barrier (rows that are not updated keep their values
+// through selects, the pivots are kept in registers and stored at the end),
+// and the reductions of column j + 1 are computed at the end of step j:
+// once column j + 1 is updated, its candidates are reduced over the wave
+// while the rest of step j's update (columns j + 2 ..) is placed between the
+// reduction's dependent steps, whose latency it fills (5.49 -> 5.31 ms for
+// the 2048 x 2048 factorization).
 constexpr int LU_W = LU_PANEL_THREADS / 64;   // waves of the panel's workgroup
 struct PanelShared {
     PanelCand cand[2][LU_W];
@@ -151,35 +175,41 @@ __device__ __forceinline__ void panel_columns(double (&v)[LU_ROWS][LU_NB], int (
     constexpr int W = LU_W;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (FULL) nb = LU_NB;
-    // the first zero pivot, kept in registers (a global read per column
-    // would stall every column's barrier on memory latency)
+    // the first zero pivot and the pivot positions, kept in registers (a
+    // global access per column would stall every column's barrier on memory
+    // latency) and stored at the end
     int32_t zero_at = info[0];
-    int piv_at[LU_NB];   // the pivot position of each column
+    int piv_at[LU_NB];
+    // pivot candidates of column j: per thread the largest |a[.][j]| among
+    // its rows at positions >= j and the smallest such position
+    double mt = 0.0;
+    int lt = 0, br = 0;
+    auto candidates = [&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        double x[LU_ROWS];
+#pragma unroll
+        for (int r = 0; r < R; r++) x[r] = (lab[r] >= j && lab[r] < m) ? fabs(v[r][j]) : -1.0;
+        mt = x[0];
+#pragma unroll
+        for (int r = 1; r < R; r++) mt = dmax(mt, x[r]);
+        lt = 0x7fffffff;
+        br = 0;
+#pragma unroll
+        for (int r = R - 1; r >= 0; r--) {
+            const bool t = x[r] == mt && lab[r] < lt;
+            lt = t ? lab[r] : lt;
+            br = t ? r : br;
+        }
+    };
+    candidates(std::integral_constant<int, 0>{});
+    double mw = wave_max(mt, lane);
+    int pwv = wave_min(mt == mw ? lt : 0x7fffffff, lane);
 
-    // columns as a compile-time sequence, so that every index into v is a
-    // constant and v stays in registers
     static_for<0, LU_NB>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         if (FULL || j < nb) {   // uniform
             constexpr int h = j & 1;
-            // ---- pivot candidates: per thread the largest |a[.][j]| among
-            // its rows at positions >= j and the smallest such position, then
-            // the same per wave
-            double x[LU_ROWS];
-#pragma unroll
-            for (int r = 0; r < R; r++) x[r] = (lab[r] >= j && lab[r] < m) ? fabs(v[r][j]) : -1.0;
-            double mt = x[0];
-#pragma unroll
-            for (int r = 1; r < R; r++) mt = dmax(mt, x[r]);
-            int lt = 0x7fffffff, br = 0;
-#pragma unroll
-            for (int r = R - 1; r >= 0; r--) {
-                const bool t = x[r] == mt && lab[r] < lt;
-                lt = t ? lab[r] : lt;
-                br = t ? r : br;
-            }
-            const double mw = wave_max(mt, lane);
-            const int pwv = wave_min(mt == mw ? lt : 0x7fffffff, lane);
+            // ---- publish the wave's candidate and its row
             if (lane == 0) sh.cand[h][wave] = PanelCand{mw, pwv, 0};
             if (lt == pwv) {   // the one lane of the wave that holds the candidate (positions are unique)
 #pragma unroll
@@ -187,7 +217,7 @@ __device__ __forceinline__ void panel_columns(double (&v)[LU_ROWS][LU_NB], int (
                     if (br == r) {
 #pragma unroll
                         for (int c = 0; c < LU_NB; c++) sh.crow[h][wave][c] = v[r][c];
-                        asm volatile("" ::: "memory");   // keeps the four stores apart (merged, they index v at run time)
+                        asm volatile("" ::: "memory");   // keeps the stores apart (merged, they index v at run time)
                     }
                 }
             }
@@ -204,21 +234,17 @@ __device__ __forceinline__ void panel_columns(double (&v)[LU_ROWS][LU_NB], int (
             p = imin(p, dpp_i<0xB1>(p));
             p = imin(p, dpp_i<0x4E>(p));
             p = imin(p, dpp_i<0x141>(p));
-            // every group of 8 lanes holds the result; the wave that published it
             const int pw = __ffsll((long long)(__ballot(lane < W && cl.row == p) & 0xffull)) - 1;
             piv_at[j] = p;
             zero_at = (b == 0.0 && zero_at == 0) ? (int32_t)(k + j + 1) : zero_at;
             const double *rowp = sh.crow[h][pw];
-            double pr[LU_NB];   // the pivot row's columns j .. LU_NB - 1, read once
+            double pr[LU_NB];
 #pragma unroll
             for (int c = j; c < LU_NB; c++) pr[c] = rowp[c];
-            // ---- exchange positions j and p
 #pragma unroll
             for (int r = 0; r < R; r++) lab[r] = lab[r] == j ? p : (lab[r] == p ? j : lab[r]);
             // ---- scale the column below the pivot (a zero pivot scales
-            // nothing), update the panel's right part; the four quotients are
-            // independent, and column j + 1 comes first: the next pivot
-            // search waits for it alone
+            // nothing); rows that are not updated keep their values
             const double piv = pr[j];
             bool up[LU_ROWS];
             double l[LU_ROWS];
@@ -229,10 +255,41 @@ __device__ __forceinline__ void panel_columns(double (&v)[LU_ROWS][LU_NB], int (
                 l[r] = q;
                 v[r][j] = up[r] ? q : v[r][j];
             }
+            auto update = [&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+                if constexpr (c < LU_NB) {
 #pragma unroll
-            for (int c = j + 1; c < LU_NB; c++) {
-#pragma unroll
-                for (int r = 0; r < R; r++) v[r][c] = up[r] ? v[r][c] - l[r] * pr[c] : v[r][c];
+                    for (int r = 0; r < R; r++) {
+                        v[r][c] = up[r] ? v[r][c] - l[r] * pr[c] : v[r][c];
+                        // computed here, not sunk to its first use (the
+                        // next column's publication)
+                        asm volatile("" : "+v"(v[r][c]));
+                    }
+                }
+            };
+            if constexpr (j + 1 < LU_NB) {
+                // ---- column j + 1 first, then its candidates and their
+                // reductions, with columns j + 2 .. between the steps
+                update(std::integral_constant<int, j + 1>{});
+                candidates(std::integral_constant<int, j + 1>{});
+                double mwn = mt;
+                static_for<0, 6>([&](auto sc) {
+                    constexpr int st = decltype(sc)::value;
+                    mwn = wave_max_step<st>(mwn, lane);
+                    update(std::integral_constant<int, j + 2 + st>{});
+                    __builtin_amdgcn_sched_barrier(0);   // keep the pairs apart: the scheduler would bunch them
+                });
+                int pwn = mt == mwn ? lt : 0x7fffffff;
+                static_for<0, 6>([&](auto sc) {
+                    constexpr int st = decltype(sc)::value;
+                    pwn = wave_min_step<st>(pwn, lane);
+                    update(std::integral_constant<int, j + 8 + st>{});
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+                update(std::integral_constant<int, j + 14>{});
+                update(std::integral_constant<int, j + 15>{});
+                mw = mwn;
+                pwv = pwn;
             }
         }
     });
@@ -252,7 +309,6 @@ __device__ __forceinline__ void panel_columns(double (&v)[LU_ROWS][LU_NB], int (
         info[0] = zero_at;
     }
 }
-
 // The first panel (and, with the lookahead off, every panel): rows k ..
 // n-1 of columns k .. k+nb-1 loaded into registers, then factored.
 template <bool FULL, int R>
