@@ -39,11 +39,6 @@ constexpr int LU_PANEL_THREADS = FB_LU_PANEL_THREADS;
 constexpr int LU_ROWS = (int)(LU_MAX_N / LU_PANEL_THREADS);   // rows of the panel per thread
 static_assert(LU_ROWS * LU_PANEL_THREADS >= LU_MAX_N, "the panel kernel holds every row of a panel");
 
-__global__ void lu_init(int32_t *info)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) info[0] = 0;
-}
-
 // ---- pivot search within a wavefront
 //
 // The pivot is the first row (smallest position) among those of largest
@@ -177,8 +172,8 @@ __device__ __forceinline__ void panel_columns(double (&v)[LU_ROWS][LU_NB], int (
     if (FULL) nb = LU_NB;
     // the first zero pivot and the pivot positions, kept in registers (a
     // global access per column would stall every column's barrier on memory
-    // latency) and stored at the end
-    int32_t zero_at = info[0];
+    // latency) and stored at the end; the first panel starts the record
+    int32_t zero_at = k == 0 ? 0 : info[0];
     int piv_at[LU_NB];
     // pivot candidates of column j: per thread the largest |a[.][j]| among
     // its rows at positions >= j and the smallest such position
@@ -884,8 +879,7 @@ static void launch_step(int64_t m, bool full_next, unsigned grid, double *a, int
 
 hipError_t launch_lu(double *a, int64_t n, int64_t lda, int32_t *ipiv, int32_t *info, hipStream_t st)
 {
-    hipLaunchKernelGGL(lu_init, dim3(1), dim3(64), 0, st, info);
-    hipError_t e = hipGetLastError();
+    hipError_t e = hipSuccess;
     if (FB_LU_LOOKAHEAD) {
         const int nb0 = (int)(n < LU_NB ? n : LU_NB);
         if (e == hipSuccess) {
