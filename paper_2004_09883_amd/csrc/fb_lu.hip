@@ -575,7 +575,7 @@ __global__ void __launch_bounds__(256)
 //                   one column per thread.
 // Every element receives the same operations in the same order as in
 // lu_swap_trsm and lu_gemm, so the factors are bitwise those of the
-// three-kernel schedule.
+// three-launch schedule.
 constexpr int LU_STAGE_LD = LU_NB + 2;   // staged row stride in doubles: 16-byte aligned rows, spread banks
 struct StripShared {
     double L[LU_NB][LU_NB + 1];          // L11
@@ -600,8 +600,7 @@ __device__ __forceinline__ void strip_update(double *__restrict__ a, int64_t n, 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = (int)(n - k);
     // ---- every load that does not depend on the permutation goes first:
-    // the strip's rows, L11 and the first half of L21 (four panel columns
-    // per quarter, two quarters in flight)
+    // the strip's first rows, the first half of L21, L11 and the pivots.
     // Every load is unconditional (rows past the end read the last row
     // again: they are never stored, published or used as candidates), so
     // that no load waits at a branch.  A strip is called with nb == LU_NB (a
